@@ -1,0 +1,200 @@
+/*
+ * frpca.h - C interface of the MI355X (gfx950) implementation of fast randomized PCA for
+ * sparse data: frPCA (Alg. 5, m <= n) and frPCAt (Alg. 6, m >= n) of Feng, Xie, Song, Yu
+ * and Tang, "Fast Randomized PCA for Sparse Data", ACML 2018.
+ *
+ * Conventions shared by every entry point
+ *  - Pointers named as device pointers must address HIP device memory of the current
+ *    device; host pointers are plain host memory. The library never takes ownership of a
+ *    caller buffer. Dense panels are row-major.
+ *  - A CSR matrix is canonical: row_ptr[0] = 0, row_ptr[m] = nnz, non-decreasing row_ptr,
+ *    column indices in [0, n) strictly increasing inside each row, finite values,
+ *    nnz < 2^31.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream). Work is
+ *    enqueued on it; calls return before the GPU finishes unless stated otherwise.
+ *  - Every entry point returns FRPCA_OK (0) or a negative status. On FRPCA_EINVAL no
+ *    output is written. frpca_last_error() describes the most recent failure.
+ *  - A handle is not thread-safe; distinct handles may be used from distinct threads.
+ */
+#ifndef FRPCA_H
+#define FRPCA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FRPCA_OK 0
+#define FRPCA_EINVAL (-1) /* bad argument or malformed CSR                          */
+#define FRPCA_ENOMEM (-2) /* device allocation failed or exceeds opts.max_workspace  */
+#define FRPCA_EHIP (-3)   /* a HIP runtime call failed                               */
+#define FRPCA_ESTATE (-4) /* call not valid in the handle's current state            */
+
+/* Kernel classes timed when opts.timing is set (indices into frpca_info.t_ms). */
+#define FRPCA_T_GAUSS 0   /* Gaussian test matrix                                    */
+#define FRPCA_T_SPMM_F 1  /* sparse x panel into the long side (A Q in Alg. 6)        */
+#define FRPCA_T_SPMM_B 2  /* sparse^T x panel back to the short side (A^T Y, Alg. 6)  */
+#define FRPCA_T_GRAM 3    /* X^T X Gram matrix (FP64 MFMA)                          */
+#define FRPCA_T_EIG 4     /* symmetric eigendecomposition of the Gram matrix         */
+#define FRPCA_T_LU 5      /* LU basis: pivot selection + factor/inverse              */
+#define FRPCA_T_TSMM 6    /* tall-skinny panel x small matrix (MFMA)                 */
+#define FRPCA_T_SIGN 7    /* output sign convention                                   */
+#define FRPCA_T_BWD 8     /* adjoint: cross-Gram, k x k terms, panels                  */
+#define FRPCA_T_SDDMM 9   /* adjoint projected onto the sparsity pattern              */
+#define FRPCA_NTIMERS 10
+
+typedef struct frpca_ctx* frpca_t;
+
+/* Options; a zero-initialised struct selects every default. */
+typedef struct {
+  int panel_bf16;       /* 1: inner-pass panels (the basis fed to the forward product and
+                           the long-side panel fed to the back product) are stored in BF16
+                           (round to nearest even) with FP32 accumulation; the final pass
+                           reads the FP32 basis. 0 (default): FP32 panels.            */
+  int no_sign_fix;      /* 0 (default): flip each (u_i, v_i) so that the largest-|.| entry
+                           of v_i is positive (ties: lowest index). 1: leave signs.      */
+  double rank_tol;      /* singular values <= rank_tol * sigma_max of the final eigSVD
+                           are reported as 0 with zero U/V columns. 0 selects 1e-5.    */
+  int timing;           /* 1: time each kernel class with HIP events (frpca_get_info). */
+  size_t max_workspace; /* 0: unlimited; else frpca_run fails with FRPCA_ENOMEM if its
+                           device workspace would exceed this many bytes.             */
+} frpca_opts;
+
+typedef struct {
+  int64_t m, n, nnz;
+  int orientation;        /* 6: Alg. 6 (m >= n); 5: Alg. 5 (m < n)                    */
+  int k, s, passes;       /* of the last frpca_run                                    */
+  int rank_dropped;       /* output singular values set to 0 by rank_tol (last run)   */
+  size_t workspace_bytes; /* device memory currently held by the handle               */
+  double create_ms;       /* wall time of frpca_create (validation + CSC mirror)       */
+  double t_ms[FRPCA_NTIMERS];   /* accumulated GPU time per kernel class (opts.timing) */
+  int64_t t_count[FRPCA_NTIMERS]; /* number of timed launches per class                */
+} frpca_info;
+
+/*
+ * frpca_create - bind a CSR matrix and build its column-major mirror.
+ * Defines: the input A of Alg. 5/6 (m x n sparse). The paper avoids forming A^T because the
+ * sparse storage makes it awkward (Section 3.2); here a column-major copy of the pattern
+ * (col_ptr, row indices, permutation into CSR order, values) is built once on the GPU by a
+ * stable sort of the nonzeros by column, so both products run without atomics.
+ * row_ptr (int64[m+1]), col (int32[nnz]), val (float[nnz]) are device pointers, borrowed:
+ * they must stay allocated and unchanged until frpca_destroy (after changing the values,
+ * call frpca_set_values). Validates the CSR on the device and synchronises `stream` once.
+ * *out receives the handle (NULL on failure). Errors: EINVAL (shape, malformed CSR,
+ * non-finite value), ENOMEM, EHIP.
+ */
+int frpca_create(frpca_t* out, int64_t m, int64_t n, int64_t nnz, const int64_t* row_ptr,
+                 const int32_t* col, const float* val, const frpca_opts* opts, void* stream);
+
+/* frpca_set_values - the CSR values changed (same pattern); refresh the mirror's values.
+ * val: device float[nnz] (borrowed as in frpca_create). Asynchronous. */
+int frpca_set_values(frpca_t h, const float* val);
+
+/* frpca_set_stream - enqueue subsequent work of h on `stream`. */
+int frpca_set_stream(frpca_t h, void* stream);
+
+/*
+ * frpca_run - rank-k truncated SVD A ~ U diag(S) V^T by Alg. 6 (m >= n) or Alg. 5 (m < n).
+ * Defines: Alg. 5 / Alg. 6 (Section 3.3) with pass parameter q = p_passes >= 2 (number of
+ * passes over A), oversampling s = s_oversample >= 0, l = k + s <= min(m, n), l <= 128;
+ * inner LU bases (Lemma 3, eq. 8) and eigSVD bases (Alg. 2); the Gaussian test matrix is
+ * drawn from Philox4x32-10 with key `seed` (element [r, j] of the rows x l draw is normal
+ * number r*l + j: Box-Muller in FP64 on words (x0,x1), (x2,x3) of block t/4, rounded to
+ * FP32). Outputs (device, row-major, caller-allocated): U float[m*k], S float[k]
+ * (descending), V float[n*k]. Sign and rank conventions: see frpca_opts.
+ * Asynchronous; the handle's workspace is (re)allocated on the first call for a larger l.
+ * Errors: EINVAL (k < 1, s < 0, k+s > min(m,n), k+s > 128, p_passes < 2), ENOMEM, EHIP.
+ */
+int frpca_run(frpca_t h, int k, int p_passes, int s_oversample, uint64_t seed, float* U,
+              float* S, float* V);
+
+/*
+ * frpca_backward - dL/d(values of A) from dL/dU, dL/dS, dL/dV through the truncated-SVD
+ * adjoint, projected onto the sparsity pattern (not part of the paper; the standard SVD
+ * reverse-mode rule): with J = U^T dU, K = V^T dV (FP64), F_ij = 1/(s_j^2 - s_i^2) (i != j,
+ * 0 where |s_j^2 - s_i^2| <= 1e-12 s_1^2), S+ = diag(1/s_i or 0),
+ *   M = (F o (J - J^T)) S + diag(dS) + S (F o (K - K^T)),
+ *   dA = U M V^T + (dU - U J) S+ V^T + U S+ (dV - V K)^T,
+ * and dval[e] = dA[row(e), col(e)] in CSR order. U (m x k), S (k), V (n x k) are the
+ * factors returned by frpca_run for the current values; dU, dS, dV may be NULL (zero).
+ * All pointers are device pointers; dval is float[nnz]. Asynchronous.
+ * Errors: EINVAL (k < 1, k > min(m, n), k > 128, NULL factor or dval), ENOMEM, EHIP.
+ */
+int frpca_backward(frpca_t h, int k, const float* U, const float* S, const float* V,
+                   const float* dU, const float* dS, const float* dV, float* dval);
+
+/* frpca_get_info - sizes, orientation, last run's parameters and timers (host struct).
+ * Synchronises the handle's stream when timing is enabled. */
+int frpca_get_info(frpca_t h, frpca_info* info);
+
+/* frpca_reset_timers - zero the accumulated kernel timers. */
+int frpca_reset_timers(frpca_t h);
+
+/* frpca_last_error - text of the most recent failure on h (h = NULL: the calling thread's
+ * most recent failure outside a handle). Valid until the next call on the same handle. */
+const char* frpca_last_error(frpca_t h);
+
+/* frpca_destroy - free all device memory held by h (synchronises its stream). */
+int frpca_destroy(frpca_t h);
+
+/* ------------------------------------------------------------------------------------
+ * Step-level entry points: one step of the path each, for tests and composition. They
+ * use the handle's stream and scratch memory, synchronise before returning, and follow
+ * the same numerical definitions as frpca_run. Panels: `l` columns, leading dimension
+ * `ld` >= l (elements); BF16 panels are uint16 bit patterns.
+ * ------------------------------------------------------------------------------------ */
+
+/* Gaussian test matrix (Alg. 5/6 "randn"): out[r*ld + j] = normal(seed, r*l + j) for
+ * r < rows, j < l; columns l..ld-1 are set to 0. out: device float[rows*ld]. */
+int frpca_gaussian(frpca_t h, uint64_t seed, int64_t rows, int l, int ld, float* out);
+
+/* Sparse x panel (the products of Alg. 5/6): trans = 0: out = A in (in: n x l, out: m x l);
+ * trans = 1: out = A^T in (in: m x l, out: n x l). FP32 accumulation; in_bf16 / out_bf16
+ * select BF16 panels. All columns below min(ld_in, ld_out, 128) rounded down to even are
+ * computed, so zero pad columns of `in` give zero pad columns of `out`. */
+int frpca_spmm(frpca_t h, int trans, int l, const void* in, int in_bf16, int ld_in, void* out,
+               int out_bf16, int ld_out);
+
+/* Gram matrix of a tall panel (Alg. 2 step 1): G = X^T X, X: device float[rows*ldx]
+ * (l columns), G: device double[l*l] row-major, accumulated in FP64 on MFMA. */
+int frpca_gram(frpca_t h, int64_t rows, int l, const float* X, int ldx, double* G);
+
+/* Symmetric eigendecomposition (Alg. 2 step 2) by cyclic parallel Jacobi in FP64:
+ * G (device double[l*l], symmetric) = W diag(d) W^T with d ascending (device double[l])
+ * and orthonormal W (device double[l*l], column j pairs with d[j]). l <= 128. */
+int frpca_eig(frpca_t h, int l, const double* G, double* W, double* d);
+
+/* eigSVD basis (Alg. 2): Q = X V diag(1/S) with S ascending; S_j <= tol * max(S) gives a
+ * zero column (tol <= 0 selects 1e-12). X, Q: device float panels (rows x l), S: device
+ * double[l] (ascending, zeroed where dropped). */
+int frpca_eigsvd(frpca_t h, int64_t rows, int l, const float* X, int ldx, float* Q, int ldq,
+                 double* S, double tol);
+
+/* LU basis (Lemma 3, eq. 8): Q = P^T L of P X = L U with pivots chosen by tournament
+ * pivoting (partial pivoting inside each node); pivot rows of Q form a unit lower-triangular
+ * block. A column whose best remaining pivot is <= tol * max|X| is zero in Q (tol <= 0
+ * selects 1e-12). *ndropped (host int) receives the number of zero columns. */
+int frpca_lu(frpca_t h, int64_t rows, int l, const float* X, int ldx, float* Q, int ldq,
+             double tol, int* ndropped);
+
+/* Tall-skinny product out = X B (rows x c), X: device float[rows*ldx] (kdim columns),
+ * B: device double[kdim*c] row-major, FP64 accumulation on MFMA, out: device float. */
+int frpca_tsmm(frpca_t h, int64_t rows, int kdim, int c, const float* X, int ldx,
+               const double* B, float* out, int ldo);
+
+/* Sampled dense-dense product on the sparsity pattern (the adjoint's projection):
+ * dval[e] = sum_i P1[r,i] Q1[c,i] + sum_i P2[r,i] Q2[c,i] for nonzero e = (r, c), CSR
+ * order; P1, P2: device float[m*w] (ld w), Q1, Q2: device float[n*w]; P2/Q2 may be NULL. */
+int frpca_sddmm(frpca_t h, int w, const float* P1, const float* Q1, const float* P2,
+                const float* Q2, float* dval);
+
+/* Copy of the column-major mirror built by frpca_create: col_ptr int64[n+1], row
+ * int32[nnz], perm int32[nnz] (CSR position of each column-major nonzero). Device ptrs. */
+int frpca_export_csc(frpca_t h, int64_t* col_ptr, int32_t* row, int32_t* perm);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FRPCA_H */

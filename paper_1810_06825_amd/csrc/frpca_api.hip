@@ -1,0 +1,736 @@
+// C interface and host orchestration of frPCA / frPCAt (Alg. 5 / Alg. 6) on gfx950.
+//
+// Both algorithms are driven by one schedule written for "the short side" (the smaller of
+// m, n, where the basis Q lives) and "the long side": the forward product maps a short-side
+// panel to the long side (A Q in Alg. 6, A^T Q in Alg. 5) and the back product maps it
+// back (A^T Y in Alg. 6, A Y in Alg. 5). Alg. 5 on A is the same computation as Alg. 6 on
+// A^T with U and V exchanged, so only the roles of the CSR matrix and its column-major
+// mirror swap. Every step is a kernel enqueued on the handle's stream; the host only
+// sequences launches.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+
+using namespace frpca;
+
+namespace {
+
+thread_local std::string g_last_error;
+constexpr double kInnerTol = 1e-12;
+constexpr double kDefaultRankTol = 1e-5;
+
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+// Bump allocator over one device allocation.
+struct Arena {
+  char* base = nullptr;
+  size_t used = 0;
+  template <class T>
+  T* take(size_t count) {
+    T* p = reinterpret_cast<T*>(base + used);
+    used += align256(count * sizeof(T));
+    return p;
+  }
+};
+
+struct DeviceTemp {
+  void* p = nullptr;
+  explicit DeviceTemp(size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error{FRPCA_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed"};
+    }
+  }
+  ~DeviceTemp() {
+    if (p) (void)hipFree(p);
+  }
+  DeviceTemp(const DeviceTemp&) = delete;
+  DeviceTemp& operator=(const DeviceTemp&) = delete;
+};
+
+__global__ void iota_kernel(uint32_t* v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = (uint32_t)i;
+}
+__global__ void widen_kernel(const int32_t* a, int64_t n, int64_t* b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = a[i];
+}
+
+int bits_for(int64_t maxval) {
+  int b = 1;
+  while (b < 32 && ((int64_t)1 << b) <= maxval) ++b;
+  return b;
+}
+
+}  // namespace
+
+struct frpca_ctx {
+  int64_t m = 0, n = 0, nnz = 0;
+  const int64_t* row_ptr = nullptr;
+  const int32_t* col = nullptr;
+  const float* val = nullptr;
+  hipStream_t stream = nullptr;
+  frpca_opts opts{};
+  double rank_tol = kDefaultRankTol;
+
+  std::vector<void*> owned;  // setup allocations
+  int32_t* rp32 = nullptr;
+  int32_t* cp32 = nullptr;
+  int32_t* row_csc = nullptr;
+  int32_t* perm = nullptr;
+  float* val_csc = nullptr;
+  MergePlan csr, csc;
+
+  // forward-run workspace
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  int ws_lp = 0;
+  int ws_bf16 = -1;
+  float *Q = nullptr, *X = nullptr, *Y = nullptr, *Z = nullptr;
+  uint16_t *Qb = nullptr, *Yb = nullptr;
+  double *gram_part = nullptr, *G = nullptr, *W = nullptr, *d = nullptr, *diag = nullptr, *rotlog = nullptr;
+  double *B1 = nullptr, *B2 = nullptr;
+  int *order = nullptr, *nsteps = nullptr, *ndrop = nullptr;
+  void *lu_tmp = nullptr, *sign_tmp = nullptr;
+
+  // backward workspace
+  void* bws = nullptr;
+  size_t bws_bytes = 0;
+  int bws_k = 0;
+
+  frpca_info info{};
+  struct Pending {
+    hipEvent_t a, b;
+    int cls;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+  std::string last_error;
+
+  size_t setup_bytes = 0;
+
+  ~frpca_ctx() {
+    if (stream) (void)hipStreamSynchronize(stream);
+    for (auto& p : pending) {
+      (void)hipEventDestroy(p.a);
+      (void)hipEventDestroy(p.b);
+    }
+    for (auto e : pool) (void)hipEventDestroy(e);
+    for (void* p : owned) (void)hipFree(p);
+    if (ws) (void)hipFree(ws);
+    if (bws) (void)hipFree(bws);
+  }
+
+  void* alloc_owned(size_t bytes) {
+    void* p = nullptr;
+    if (bytes == 0) bytes = 256;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error{FRPCA_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed"};
+    }
+    owned.push_back(p);
+    setup_bytes += bytes;
+    return p;
+  }
+
+  hipEvent_t get_event() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    FRPCA_HIP(hipEventCreate(&e));
+    return e;
+  }
+
+  // RAII timing of one kernel class on the handle's stream (when opts.timing is set).
+  struct Scope {
+    frpca_ctx* h;
+    int cls;
+    hipEvent_t a = nullptr;
+    Scope(frpca_ctx* h_, int cls_) : h(h_), cls(cls_) {
+      if (h->opts.timing) {
+        a = h->get_event();
+        FRPCA_HIP(hipEventRecord(a, h->stream));
+      }
+    }
+    ~Scope() {
+      if (a) {
+        hipEvent_t b = h->get_event();
+        (void)hipEventRecord(b, h->stream);
+        h->pending.push_back({a, b, cls});
+      }
+    }
+  };
+
+  void collect_timers() {
+    if (pending.empty()) return;
+    FRPCA_HIP(hipStreamSynchronize(stream));
+    for (auto& p : pending) {
+      float ms = 0.f;
+      FRPCA_HIP(hipEventElapsedTime(&ms, p.a, p.b));
+      info.t_ms[p.cls] += ms;
+      info.t_count[p.cls] += 1;
+      pool.push_back(p.a);
+      pool.push_back(p.b);
+    }
+    pending.clear();
+  }
+
+  void build_plan(MergePlan& p, const int32_t* ptr, const int32_t* idx, const float* v, int64_t nseg) {
+    p.ptr = ptr;
+    p.idx = idx;
+    p.val = v;
+    p.nseg = nseg;
+    p.nnz = nnz;
+    p.ipw = merge_items_per_wave(nseg, nnz);
+    p.nwaves = std::max<int64_t>(1, (nseg + nnz + p.ipw - 1) / p.ipw);
+    p.part_seg = static_cast<int32_t*>(alloc_owned((p.nwaves + 1) * sizeof(int32_t)));
+    p.part_e = static_cast<int32_t*>(alloc_owned((p.nwaves + 1) * sizeof(int32_t)));
+    p.fix_w0 = static_cast<int32_t*>(alloc_owned(p.nwaves * sizeof(int32_t)));
+    p.carry = static_cast<float*>(alloc_owned(p.nwaves * 128 * sizeof(float)));
+    p.head = static_cast<float*>(alloc_owned(p.nwaves * 128 * sizeof(float)));
+    launch_merge_partition(p, stream);
+    launch_merge_fixplan(p, stream);
+  }
+
+  int64_t short_rows() const { return std::min(m, n); }
+  int64_t long_rows() const { return std::max(m, n); }
+
+  void ensure_workspace(int lp, int bf16) {
+    if (ws && ws_lp >= lp && ws_bf16 == bf16) return;
+    if (ws) {
+      FRPCA_HIP(hipStreamSynchronize(stream));
+      FRPCA_HIP(hipFree(ws));
+      ws = nullptr;
+      ws_bytes = 0;
+    }
+    const int64_t Ns = short_rows(), Nl = long_rows();
+    auto plan = [&](Arena& a) {
+      Q = a.take<float>((size_t)Ns * lp);
+      X = a.take<float>((size_t)Ns * lp);
+      Qb = bf16 ? a.take<uint16_t>((size_t)Ns * lp) : nullptr;
+      Z = a.take<float>((size_t)Nl * lp);
+      Y = bf16 ? nullptr : Z;
+      Yb = bf16 ? a.take<uint16_t>((size_t)Nl * lp) : nullptr;
+      gram_part = a.take<double>(gram_partial_bytes(lp) / sizeof(double));
+      G = a.take<double>(kMaxL * kMaxL);
+      W = a.take<double>(kMaxL * kMaxL);
+      B1 = a.take<double>(kMaxL * kMaxL);
+      B2 = a.take<double>(kMaxL * kMaxL);
+      d = a.take<double>(kMaxL);
+      diag = a.take<double>(kMaxL);
+      order = a.take<int>(kMaxL);
+      nsteps = a.take<int>(4);
+      ndrop = a.take<int>(4);
+      rotlog = a.take<double>(eig_log_bytes(lp) / sizeof(double));
+      lu_tmp = a.take<char>(lu_temp_bytes(Ns, lp));
+      sign_tmp = a.take<char>(sign_partial_bytes(Nl, kMaxL));
+    };
+    Arena probe;
+    plan(probe);
+    const size_t need = probe.used;
+    if (opts.max_workspace && need + setup_bytes > opts.max_workspace)
+      throw Error{FRPCA_ENOMEM, "workspace of " + std::to_string(need) + " bytes exceeds opts.max_workspace"};
+    if (hipMalloc(&ws, need) != hipSuccess) {
+      (void)hipGetLastError();
+      ws = nullptr;
+      throw Error{FRPCA_ENOMEM, "workspace allocation of " + std::to_string(need) + " bytes failed"};
+    }
+    Arena real;
+    real.base = static_cast<char*>(ws);
+    plan(real);
+    ws_bytes = need;
+    ws_lp = lp;
+    ws_bf16 = bf16;
+  }
+};
+
+namespace {
+
+int fail(frpca_t h, const Error& e) {
+  if (h) h->last_error = e.msg;
+  else g_last_error = e.msg;
+  return e.code;
+}
+
+template <class F>
+int guarded(frpca_t h, F&& f) {
+  try {
+    f();
+    return FRPCA_OK;
+  } catch (const Error& e) {
+    return fail(h, e);
+  } catch (const std::exception& e) {
+    return fail(h, Error{FRPCA_EHIP, e.what()});
+  }
+}
+
+void check_launch() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw Error{FRPCA_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e)};
+}
+
+}  // namespace
+
+extern "C" {
+
+int frpca_create(frpca_t* out, int64_t m, int64_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col,
+                 const float* val, const frpca_opts* opts, void* stream) {
+  if (out) *out = nullptr;
+  frpca_ctx* h = nullptr;
+  int rc = guarded(nullptr, [&] {
+    FRPCA_CHECK(out != nullptr, FRPCA_EINVAL, "out handle pointer is NULL");
+    FRPCA_CHECK(m >= 1 && n >= 1 && m < INT32_MAX && n < INT32_MAX, FRPCA_EINVAL,
+                "need 1 <= m, n < 2^31");
+    FRPCA_CHECK(nnz >= 0 && nnz < INT32_MAX, FRPCA_EINVAL, "need 0 <= nnz < 2^31");
+    FRPCA_CHECK(row_ptr != nullptr && (nnz == 0 || (col != nullptr && val != nullptr)), FRPCA_EINVAL,
+                "NULL CSR array");
+    if (opts) FRPCA_CHECK(opts->rank_tol >= 0.0 && opts->rank_tol < 1.0, FRPCA_EINVAL, "rank_tol must be in [0, 1)");
+    const auto t0 = std::chrono::steady_clock::now();
+    h = new frpca_ctx();
+    h->m = m;
+    h->n = n;
+    h->nnz = nnz;
+    h->row_ptr = row_ptr;
+    h->col = col;
+    h->val = val;
+    h->stream = static_cast<hipStream_t>(stream);
+    if (opts) h->opts = *opts;
+    h->rank_tol = h->opts.rank_tol > 0.0 ? h->opts.rank_tol : kDefaultRankTol;
+    hipStream_t st = h->stream;
+
+    {  // validation on the device, one synchronisation
+      int* flag = static_cast<int*>(h->alloc_owned(sizeof(int)));
+      FRPCA_HIP(hipMemsetAsync(flag, 0, sizeof(int), st));
+      launch_validate_csr(m, n, nnz, row_ptr, col, val, flag, st);
+      check_launch();
+      int hflag = 0;
+      FRPCA_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+      FRPCA_HIP(hipStreamSynchronize(st));
+      if (hflag) {
+        std::string why = "malformed CSR:";
+        if (hflag & 1) why += " row_ptr[0] != 0 or row_ptr[m] != nnz or out of range;";
+        if (hflag & 2) why += " row_ptr decreasing;";
+        if (hflag & 4) why += " column index out of [0, n);";
+        if (hflag & 8) why += " columns not strictly increasing within a row;";
+        if (hflag & 16) why += " non-finite value;";
+        throw Error{FRPCA_EINVAL, why};
+      }
+    }
+    h->rp32 = static_cast<int32_t*>(h->alloc_owned((m + 1) * sizeof(int32_t)));
+    launch_ptr_to_i32(row_ptr, m + 1, h->rp32, st);
+    h->cp32 = static_cast<int32_t*>(h->alloc_owned((n + 1) * sizeof(int32_t)));
+    h->row_csc = static_cast<int32_t*>(h->alloc_owned(std::max<int64_t>(nnz, 1) * sizeof(int32_t)));
+    h->perm = static_cast<int32_t*>(h->alloc_owned(std::max<int64_t>(nnz, 1) * sizeof(int32_t)));
+    h->val_csc = static_cast<float*>(h->alloc_owned(std::max<int64_t>(nnz, 1) * sizeof(float)));
+    {
+      // stable sort of CSR positions by column gives the column-major order
+      const size_t nb = std::max<int64_t>(nnz, 1) * sizeof(uint32_t);
+      DeviceTemp keys(nb), keys_alt(nb), vals_alt(nb), row_of(nb), counts((n + 1) * sizeof(int32_t));
+      DeviceTemp rtmp(radix_temp_bytes(nnz)), stmp(scan_temp_bytes(n));
+      uint32_t* kk = static_cast<uint32_t*>(keys.p);
+      uint32_t* vv = reinterpret_cast<uint32_t*>(h->perm);
+      if (nnz > 0) {
+        FRPCA_HIP(hipMemcpyAsync(kk, col, nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+        iota_kernel<<<(unsigned)((nnz + 255) / 256), 256, 0, st>>>(vv, nnz);
+        radix_sort_pairs(kk, vv, static_cast<uint32_t*>(keys_alt.p), static_cast<uint32_t*>(vals_alt.p), nnz,
+                         bits_for(n - 1), rtmp.p, st);
+      }
+      FRPCA_HIP(hipMemsetAsync(counts.p, 0, (n + 1) * sizeof(int32_t), st));
+      launch_count_keys(col, nnz, static_cast<int32_t*>(counts.p), st);
+      exclusive_scan_i32(static_cast<int32_t*>(counts.p), h->cp32, n, stmp.p, st);
+      launch_expand_rows(h->rp32, m, nnz, static_cast<int32_t*>(row_of.p), st);
+      launch_gather_csc(vv, static_cast<int32_t*>(row_of.p), val, nnz, h->row_csc, h->val_csc, st);
+      check_launch();
+      h->build_plan(h->csr, h->rp32, col, val, m);
+      h->build_plan(h->csc, h->cp32, h->row_csc, h->val_csc, n);
+      check_launch();
+      FRPCA_HIP(hipStreamSynchronize(st));
+    }
+    h->info.m = m;
+    h->info.n = n;
+    h->info.nnz = nnz;
+    h->info.orientation = m >= n ? 6 : 5;
+    h->info.create_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  });
+  if (rc != FRPCA_OK) {
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return FRPCA_OK;
+}
+
+int frpca_set_values(frpca_t h, const float* val) {
+  if (!h) return fail(nullptr, Error{FRPCA_EINVAL, "NULL handle"});
+  return guarded(h, [&] {
+    FRPCA_CHECK(val != nullptr || h->nnz == 0, FRPCA_EINVAL, "NULL values");
+    h->val = val;
+    h->csr.val = val;
+    launch_gather_values(h->perm, val, h->nnz, h->val_csc, h->stream);
+    check_launch();
+  });
+}
+
+int frpca_set_stream(frpca_t h, void* stream) {
+  if (!h) return fail(nullptr, Error{FRPCA_EINVAL, "NULL handle"});
+  h->stream = static_cast<hipStream_t>(stream);
+  return FRPCA_OK;
+}
+
+int frpca_run(frpca_t h, int k, int p_passes, int s_oversample, uint64_t seed, float* U, float* S, float* V) {
+  if (!h) return fail(nullptr, Error{FRPCA_EINVAL, "NULL handle"});
+  return guarded(h, [&] {
+    const int64_t m = h->m, n = h->n;
+    FRPCA_CHECK(k >= 1 && s_oversample >= 0, FRPCA_EINVAL, "need k >= 1 and s >= 0");
+    const int l = k + s_oversample;
+    FRPCA_CHECK(l <= std::min(m, n), FRPCA_EINVAL, "need k + s <= min(m, n)");
+    FRPCA_CHECK(l <= kMaxL, FRPCA_EINVAL, "need k + s <= 128");
+    FRPCA_CHECK(p_passes >= 2, FRPCA_EINVAL, "the pass parameter q must be >= 2 (Alg. 5/6)");
+    FRPCA_CHECK(U && S && V, FRPCA_EINVAL, "NULL output");
+    const int LP = panel_ld(l);
+    const int bf = h->opts.panel_bf16 ? 1 : 0;
+    h->ensure_workspace(LP, bf);
+    hipStream_t st = h->stream;
+    const bool a6 = m >= n;
+    const MergePlan& Fp = a6 ? h->csr : h->csc;  // short side -> long side
+    const MergePlan& Bp = a6 ? h->csc : h->csr;  // long side -> short side
+    const int64_t Ns = h->short_rows(), Nl = h->long_rows();
+    const int fwd_cls = FRPCA_T_SPMM_F, back_cls = FRPCA_T_SPMM_B;
+
+    auto forward_inner = [&] {
+      frpca_ctx::Scope t(h, fwd_cls);
+      if (bf) launch_spmm(Fp, LP, h->Qb, true, LP, nullptr, h->Yb, LP, st);
+      else launch_spmm(Fp, LP, h->Q, false, LP, h->Y, nullptr, LP, st);
+    };
+    auto back = [&] {
+      frpca_ctx::Scope t(h, back_cls);
+      if (bf) launch_spmm(Bp, LP, h->Yb, true, LP, h->X, nullptr, LP, st);
+      else launch_spmm(Bp, LP, h->Y, false, LP, h->X, nullptr, LP, st);
+    };
+    auto basis_from_B1 = [&] {
+      frpca_ctx::Scope t(h, FRPCA_T_TSMM);
+      launch_tsmm(h->X, false, LP, Ns, l, h->B1, LP, l, LP, h->Q, LP, bf ? h->Qb : nullptr, LP, false, st);
+    };
+    auto orth_lu = [&] {
+      {
+        frpca_ctx::Scope t(h, FRPCA_T_LU);
+        launch_lu_coeffs(h->X, LP, Ns, l, kInnerTol, h->B1, LP, h->lu_tmp, h->ndrop + 1, st);
+      }
+      basis_from_B1();
+    };
+    auto gram_eig = [&](const float* P, int64_t rows) {
+      {
+        frpca_ctx::Scope t(h, FRPCA_T_GRAM);
+        launch_gram(P, false, LP, nullptr, 0, rows, l, h->gram_part, h->G, l, st);
+      }
+      frpca_ctx::Scope t(h, FRPCA_T_EIG);
+      launch_eig(h->G, l, l, h->d, h->W, h->rotlog, h->nsteps, h->order, h->diag, st);
+    };
+    auto orth_eig = [&] {
+      gram_eig(h->X, Ns);
+      launch_eigsvd_coeffs(h->d, h->W, l, LP, kInnerTol, h->B1, nullptr, st);
+      basis_from_B1();
+    };
+
+    // start of the pass schedule
+    if (p_passes % 2 == 0) {
+      {
+        frpca_ctx::Scope t(h, FRPCA_T_GAUSS);  // long-side Gaussian (the transposed randn(k+s, .))
+        launch_gaussian(seed, Nl, l, LP, bf ? nullptr : h->Y, bf ? h->Yb : nullptr, st);
+      }
+      back();
+      if (p_passes == 2) orth_eig();
+      else orth_lu();
+    } else {
+      frpca_ctx::Scope t(h, FRPCA_T_GAUSS);
+      launch_gaussian(seed, Ns, l, LP, h->Q, bf ? h->Qb : nullptr, st);
+    }
+    const int last = (p_passes - 1) / 2;
+    for (int i = 1; i <= last; ++i) {
+      forward_inner();
+      back();
+      if (i == last) orth_eig();
+      else orth_lu();
+    }
+    // final pass and Rayleigh-Ritz: eigSVD of the long-side panel Z
+    {
+      frpca_ctx::Scope t(h, fwd_cls);
+      launch_spmm(Fp, LP, h->Q, false, LP, h->Z, nullptr, LP, st);
+    }
+    gram_eig(h->Z, Nl);
+    launch_final_coeffs(h->d, h->W, l, k, LP, h->rank_tol, h->B1, h->B2, S, h->ndrop, st);
+    // B1 multiplies the long-side panel Z, B2 the short-side basis Q
+    float* out_long = a6 ? U : V;
+    float* out_short = a6 ? V : U;
+    auto tsmm_long = [&] {
+      frpca_ctx::Scope t(h, FRPCA_T_TSMM);
+      launch_tsmm(h->Z, false, LP, Nl, l, h->B1, LP, k, k, out_long, k, nullptr, 0, false, st);
+    };
+    auto tsmm_short = [&] {
+      frpca_ctx::Scope t(h, FRPCA_T_TSMM);
+      launch_tsmm(h->Q, false, LP, Ns, l, h->B2, LP, k, k, out_short, k, nullptr, 0, false, st);
+    };
+    if (a6) {  // V is the short-side output: build it, fix signs, then U
+      tsmm_short();
+      if (!h->opts.no_sign_fix) {
+        frpca_ctx::Scope t(h, FRPCA_T_SIGN);
+        launch_sign_fix(V, n, k, h->B1, LP, l, h->sign_tmp, st);
+      }
+      tsmm_long();
+    } else {
+      tsmm_long();
+      if (!h->opts.no_sign_fix) {
+        frpca_ctx::Scope t(h, FRPCA_T_SIGN);
+        launch_sign_fix(V, n, k, h->B2, LP, l, h->sign_tmp, st);
+      }
+      tsmm_short();
+    }
+    check_launch();
+    h->info.k = k;
+    h->info.s = s_oversample;
+    h->info.passes = p_passes;
+  });
+}
+
+int frpca_backward(frpca_t h, int k, const float* U, const float* S, const float* V, const float* dU,
+                   const float* dS, const float* dV, float* dval) {
+  if (!h) return fail(nullptr, Error{FRPCA_EINVAL, "NULL handle"});
+  return guarded(h, [&] {
+    const int64_t m = h->m, n = h->n;
+    FRPCA_CHECK(k >= 1 && k <= std::min<int64_t>(std::min(m, n), kMaxL), FRPCA_EINVAL,
+                "need 1 <= k <= min(m, n, 128)");
+    FRPCA_CHECK(U && S && V && dval, FRPCA_EINVAL, "NULL factor or output");
+    hipStream_t st = h->stream;
+    if (!h->bws || h->bws_k < k) {
+      if (h->bws) {
+        FRPCA_HIP(hipStreamSynchronize(st));
+        FRPCA_HIP(hipFree(h->bws));
+        h->bws = nullptr;
+      }
+      Arena probe;
+      probe.take<double>(gram_partial_bytes(k) / sizeof(double));
+      probe.take<double>(5 * (size_t)k * k);
+      probe.take<float>((size_t)m * k);
+      probe.take<float>((size_t)n * k);
+      if (h->opts.max_workspace && probe.used + h->setup_bytes + h->ws_bytes > h->opts.max_workspace)
+        throw Error{FRPCA_ENOMEM, "backward workspace exceeds opts.max_workspace"};
+      if (hipMalloc(&h->bws, probe.used) != hipSuccess) {
+        (void)hipGetLastError();
+        h->bws = nullptr;
+        throw Error{FRPCA_ENOMEM, "backward workspace allocation failed"};
+      }
+      h->bws_bytes = probe.used;
+      h->bws_k = k;
+    }
+    Arena a;
+    a.base = static_cast<char*>(h->bws);
+    double* part = a.take<double>(gram_partial_bytes(k) / sizeof(double));
+    double* J = a.take<double>((size_t)k * k);
+    double* K = a.take<double>((size_t)k * k);
+    double* CU = a.take<double>((size_t)k * k);
+    double* CV = a.take<double>((size_t)k * k);
+    double* SP = a.take<double>((size_t)k * k);
+    float* L1 = a.take<float>((size_t)m * k);
+    float* R2 = a.take<float>((size_t)n * k);
+    {
+      frpca_ctx::Scope t(h, FRPCA_T_BWD);
+      if (dU) launch_gram(U, false, k, dU, k, m, k, part, J, k, st);
+      if (dV) launch_gram(V, false, k, dV, k, n, k, part, K, k, st);
+      launch_adjoint_small(J, K, S, dS, k, dU != nullptr, dV != nullptr, CU, CV, SP, st);
+      launch_tsmm(U, false, k, m, k, CU, k, k, k, L1, k, nullptr, 0, false, st);
+      if (dU) launch_tsmm(dU, false, k, m, k, SP, k, k, k, L1, k, nullptr, 0, true, st);
+      if (dV) {
+        launch_tsmm(V, false, k, n, k, CV, k, k, k, R2, k, nullptr, 0, false, st);
+        launch_tsmm(dV, false, k, n, k, SP, k, k, k, R2, k, nullptr, 0, true, st);
+      }
+    }
+    {
+      frpca_ctx::Scope t(h, FRPCA_T_SDDMM);
+      launch_sddmm(h->rp32, h->col, m, k, L1, V, dV ? U : nullptr, dV ? R2 : nullptr, dval, st);
+    }
+    check_launch();
+  });
+}
+
+int frpca_get_info(frpca_t h, frpca_info* info) {
+  if (!h) return fail(nullptr, Error{FRPCA_EINVAL, "NULL handle"});
+  return guarded(h, [&] {
+    FRPCA_CHECK(info != nullptr, FRPCA_EINVAL, "NULL info");
+    h->collect_timers();
+    if (h->ws) {
+      int nd = 0;
+      FRPCA_HIP(hipMemcpyAsync(&nd, h->ndrop, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+      FRPCA_HIP(hipStreamSynchronize(h->stream));
+      h->info.rank_dropped = nd;
+    }
+    h->info.workspace_bytes = h->setup_bytes + h->ws_bytes + h->bws_bytes;
+    *info = h->info;
+  });
+}
+
+int frpca_reset_timers(frpca_t h) {
+  if (!h) return fail(nullptr, Error{FRPCA_EINVAL, "NULL handle"});
+  return guarded(h, [&] {
+    h->collect_timers();
+    for (int i = 0; i < FRPCA_NTIMERS; ++i) {
+      h->info.t_ms[i] = 0.0;
+      h->info.t_count[i] = 0;
+    }
+  });
+}
+
+const char* frpca_last_error(frpca_t h) { return h ? h->last_error.c_str() : g_last_error.c_str(); }
+
+int frpca_destroy(frpca_t h) {
+  delete h;
+  return FRPCA_OK;
+}
+
+// ------------------------------------------------------------------ step-level entry points
+int frpca_gaussian(frpca_t h, uint64_t seed, int64_t rows, int l, int ld, float* out) {
+  if (!h) return fail(nullptr, Error{FRPCA_EINVAL, "NULL handle"});
+  return guarded(h, [&] {
+    FRPCA_CHECK(rows >= 0 && l >= 1 && ld >= l && out, FRPCA_EINVAL, "need rows >= 0, 1 <= l <= ld");
+    launch_gaussian(seed, rows, l, ld, out, nullptr, h->stream);
+    check_launch();
+    FRPCA_HIP(hipStreamSynchronize(h->stream));
+  });
+}
+
+int frpca_spmm(frpca_t h, int trans, int l, const void* in, int in_bf16, int ld_in, void* out, int out_bf16,
+               int ld_out) {
+  if (!h) return fail(nullptr, Error{FRPCA_EINVAL, "NULL handle"});
+  return guarded(h, [&] {
+    // all columns up to the common leading dimension are computed (pads included)
+    const int lp = std::min(std::min(ld_in, ld_out), kMaxL) & ~1;
+    FRPCA_CHECK(l >= 1 && l <= kMaxL && lp >= l, FRPCA_EINVAL,
+                "need 1 <= l <= 128 and leading dimensions >= l (rounded up to even)");
+    FRPCA_CHECK(in && out, FRPCA_EINVAL, "NULL panel");
+    const MergePlan& p = trans ? h->csc : h->csr;
+    launch_spmm(p, lp, in, in_bf16 != 0, ld_in, out_bf16 ? nullptr : static_cast<float*>(out),
+                out_bf16 ? static_cast<uint16_t*>(out) : nullptr, ld_out, h->stream);
+    check_launch();
+    FRPCA_HIP(hipStreamSynchronize(h->stream));
+  });
+}
+
+int frpca_gram(frpca_t h, int64_t rows, int l, const float* X, int ldx, double* G) {
+  if (!h) return fail(nullptr, Error{FRPCA_EINVAL, "NULL handle"});
+  return guarded(h, [&] {
+    FRPCA_CHECK(rows >= 0 && l >= 1 && l <= kMaxL && ldx >= l && X && G, FRPCA_EINVAL, "bad Gram arguments");
+    DeviceTemp part(gram_partial_bytes(l));
+    launch_gram(X, false, ldx, nullptr, 0, rows, l, static_cast<double*>(part.p), G, l, h->stream);
+    check_launch();
+    FRPCA_HIP(hipStreamSynchronize(h->stream));
+  });
+}
+
+int frpca_eig(frpca_t h, int l, const double* G, double* W, double* d) {
+  if (!h) return fail(nullptr, Error{FRPCA_EINVAL, "NULL handle"});
+  return guarded(h, [&] {
+    FRPCA_CHECK(l >= 1 && l <= kMaxL && G && W && d, FRPCA_EINVAL, "bad eig arguments");
+    DeviceTemp rot(eig_log_bytes(l)), misc(4096);
+    int* nsteps = static_cast<int*>(misc.p);
+    int* order = nsteps + 64;
+    double* diag = reinterpret_cast<double*>(static_cast<char*>(misc.p) + 2048);
+    launch_eig(G, l, l, d, W, static_cast<double*>(rot.p), nsteps, order, diag, h->stream);
+    check_launch();
+    FRPCA_HIP(hipStreamSynchronize(h->stream));
+  });
+}
+
+int frpca_eigsvd(frpca_t h, int64_t rows, int l, const float* X, int ldx, float* Q, int ldq, double* S,
+                 double tol) {
+  if (!h) return fail(nullptr, Error{FRPCA_EINVAL, "NULL handle"});
+  return guarded(h, [&] {
+    FRPCA_CHECK(rows >= l && l >= 1 && l <= kMaxL && ldx >= l && ldq >= l && X && Q && S, FRPCA_EINVAL,
+                "bad eigSVD arguments (need rows >= l)");
+    if (tol <= 0.0) tol = kInnerTol;
+    DeviceTemp part(gram_partial_bytes(l)), rot(eig_log_bytes(l)), misc(6 * kMaxL * kMaxL * sizeof(double));
+    double* G = static_cast<double*>(misc.p);
+    double* W = G + kMaxL * kMaxL;
+    double* B = W + kMaxL * kMaxL;
+    double* d = B + kMaxL * kMaxL;
+    double* diag = d + kMaxL;
+    int* nsteps = reinterpret_cast<int*>(diag + kMaxL);
+    int* order = nsteps + 64;
+    hipStream_t st = h->stream;
+    launch_gram(X, false, ldx, nullptr, 0, rows, l, static_cast<double*>(part.p), G, l, st);
+    launch_eig(G, l, l, d, W, static_cast<double*>(rot.p), nsteps, order, diag, st);
+    launch_eigsvd_coeffs(d, W, l, l, tol, B, S, st);
+    launch_tsmm(X, false, ldx, rows, l, B, l, l, l, Q, ldq, nullptr, 0, false, st);
+    check_launch();
+    FRPCA_HIP(hipStreamSynchronize(st));
+  });
+}
+
+int frpca_lu(frpca_t h, int64_t rows, int l, const float* X, int ldx, float* Q, int ldq, double tol,
+             int* ndropped) {
+  if (!h) return fail(nullptr, Error{FRPCA_EINVAL, "NULL handle"});
+  return guarded(h, [&] {
+    FRPCA_CHECK(rows >= 1 && l >= 1 && l <= kMaxL && ldx >= l && ldq >= l && X && Q, FRPCA_EINVAL,
+                "bad LU arguments");
+    if (tol <= 0.0) tol = kInnerTol;
+    DeviceTemp tmp(lu_temp_bytes(rows, l)), B(kMaxL * kMaxL * sizeof(double)), nd(256);
+    hipStream_t st = h->stream;
+    launch_lu_coeffs(X, ldx, rows, l, tol, static_cast<double*>(B.p), l, tmp.p, static_cast<int*>(nd.p), st);
+    launch_tsmm(X, false, ldx, rows, l, static_cast<double*>(B.p), l, l, l, Q, ldq, nullptr, 0, false, st);
+    check_launch();
+    int hnd = 0;
+    FRPCA_HIP(hipMemcpyAsync(&hnd, nd.p, sizeof(int), hipMemcpyDeviceToHost, st));
+    FRPCA_HIP(hipStreamSynchronize(st));
+    if (ndropped) *ndropped = hnd;
+  });
+}
+
+int frpca_tsmm(frpca_t h, int64_t rows, int kdim, int c, const float* X, int ldx, const double* B, float* out,
+               int ldo) {
+  if (!h) return fail(nullptr, Error{FRPCA_EINVAL, "NULL handle"});
+  return guarded(h, [&] {
+    FRPCA_CHECK(rows >= 0 && kdim >= 1 && kdim <= kMaxL && c >= 1 && c <= kMaxL && ldx >= kdim && ldo >= c && X &&
+                    B && out,
+                FRPCA_EINVAL, "bad TSMM arguments");
+    launch_tsmm(X, false, ldx, rows, kdim, B, c, c, c, out, ldo, nullptr, 0, false, h->stream);
+    check_launch();
+    FRPCA_HIP(hipStreamSynchronize(h->stream));
+  });
+}
+
+int frpca_sddmm(frpca_t h, int w, const float* P1, const float* Q1, const float* P2, const float* Q2,
+                float* dval) {
+  if (!h) return fail(nullptr, Error{FRPCA_EINVAL, "NULL handle"});
+  return guarded(h, [&] {
+    FRPCA_CHECK(w >= 1 && w <= kMaxL && P1 && Q1 && dval && ((P2 == nullptr) == (Q2 == nullptr)), FRPCA_EINVAL,
+                "bad SDDMM arguments");
+    launch_sddmm(h->rp32, h->col, h->m, w, P1, Q1, P2, Q2, dval, h->stream);
+    check_launch();
+    FRPCA_HIP(hipStreamSynchronize(h->stream));
+  });
+}
+
+int frpca_export_csc(frpca_t h, int64_t* col_ptr, int32_t* row, int32_t* perm) {
+  if (!h) return fail(nullptr, Error{FRPCA_EINVAL, "NULL handle"});
+  return guarded(h, [&] {
+    FRPCA_CHECK(col_ptr && (h->nnz == 0 || (row && perm)), FRPCA_EINVAL, "NULL output");
+    hipStream_t st = h->stream;
+    widen_kernel<<<(unsigned)((h->n + 1 + 255) / 256), 256, 0, st>>>(h->cp32, h->n + 1, col_ptr);
+    if (h->nnz) {
+      FRPCA_HIP(hipMemcpyAsync(row, h->row_csc, h->nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+      FRPCA_HIP(hipMemcpyAsync(perm, h->perm, h->nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    }
+    check_launch();
+    FRPCA_HIP(hipStreamSynchronize(st));
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,93 @@
+// Adjoint of the truncated SVD projected on the sparsity pattern (the differentiated form).
+//
+// With J = U^T dU, K = V^T dV, F_ij = 1/(s_j^2 - s_i^2) (i != j; 0 when the gap is <= 1e-12
+// s_1^2) and S+ = diag(1/s or 0), the gradient
+//   dA = U M V^T + (dU - U J) S+ V^T + U S+ (dV - V K)^T,
+//   M  = (F o (J - J^T)) S + diag(dS) + S (F o (K - K^T)),
+// is regrouped as dA = L1 V^T + U R2^T with L1 = U (M - J S+) + dU S+ and R2 = (dV - V K) S+,
+// so only its values at the stored nonzeros are formed: dval[e] = L1[r].V[c] + U[r].R2[c]
+// (sampled dense-dense product, SDDMM). The k x k algebra runs in FP64 in one workgroup.
+#include "kernels.h"
+
+namespace frpca {
+namespace {
+
+__global__ __launch_bounds__(256) void adjoint_small_kernel(const double* J, const double* K, const float* S,
+                                                            const float* dS, int k, int has_du, int has_dv,
+                                                            double* CU, double* CV, double* SP) {
+  const double s1 = (double)S[0];
+  const double gap_tol = 1e-12 * s1 * s1;
+  for (int idx = threadIdx.x; idx < k * k; idx += blockDim.x) {
+    const int i = idx / k, j = idx - i * k;
+    const double si = (double)S[i], sj = (double)S[j];
+    const double spj = sj > 0.0 ? 1.0 / sj : 0.0;
+    double F = 0.0;
+    if (i != j) {
+      const double d = sj * sj - si * si;
+      if (fabs(d) > gap_tol) F = 1.0 / d;
+    }
+    double m = 0.0;
+    double jij = 0.0;
+    if (has_du) {
+      jij = J[idx];
+      m += F * (jij - J[j * k + i]) * sj;
+    }
+    if (has_dv) m += si * F * (K[idx] - K[j * k + i]);
+    if (i == j && dS) m += (double)dS[i];
+    CU[idx] = m - jij * spj;
+    CV[idx] = has_dv ? -K[idx] * spj : 0.0;
+    SP[idx] = (i == j) ? spj : 0.0;
+  }
+}
+
+// One wave per row: lanes hold two columns of P1[r] / P2[r], gather Q1[c] / Q2[c] per
+// nonzero and reduce across the wave in a fixed butterfly order.
+__global__ __launch_bounds__(256) void sddmm_kernel(const int32_t* rp, const int32_t* col, int64_t m, int w,
+                                                    const float* P1, const float* Q1, const float* P2,
+                                                    const float* Q2, float* dval) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave0 = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t wstride = (int64_t)gridDim.x * 4;
+  const int c0 = 2 * lane, c1 = 2 * lane + 1;
+  const bool a0 = c0 < w, a1 = c1 < w;
+  for (int64_t r = wave0; r < m; r += wstride) {
+    const float* p1 = P1 + (size_t)r * w;
+    const float x0 = a0 ? p1[c0] : 0.f, x1 = a1 ? p1[c1] : 0.f;
+    float y0 = 0.f, y1 = 0.f;
+    if (P2) {
+      const float* p2 = P2 + (size_t)r * w;
+      y0 = a0 ? p2[c0] : 0.f;
+      y1 = a1 ? p2[c1] : 0.f;
+    }
+    const int e0 = rp[r], e1 = rp[r + 1];
+    for (int e = e0; e < e1; ++e) {
+      const int c = col[e];
+      const float* q1 = Q1 + (size_t)c * w;
+      float part = (a0 ? x0 * q1[c0] : 0.f) + (a1 ? x1 * q1[c1] : 0.f);
+      if (Q2) {
+        const float* q2 = Q2 + (size_t)c * w;
+        part += (a0 ? y0 * q2[c0] : 0.f) + (a1 ? y1 * q2[c1] : 0.f);
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
+      if (lane == 0) dval[e] = part;
+    }
+  }
+}
+
+}  // namespace
+
+void launch_adjoint_small(const double* J, const double* K, const float* S, const float* dS, int k, bool has_du,
+                          bool has_dv, double* CU, double* CV, double* SP, hipStream_t st) {
+  adjoint_small_kernel<<<1, 256, 0, st>>>(J, K, S, dS, k, has_du ? 1 : 0, has_dv ? 1 : 0, CU, CV, SP);
+}
+
+void launch_sddmm(const int32_t* rp, const int32_t* col, int64_t m, int w, const float* P1, const float* Q1,
+                  const float* P2, const float* Q2, float* dval, hipStream_t st) {
+  if (m <= 0) return;
+  int64_t grid = (m + 3) / 4;
+  if (grid > 65536) grid = 65536;
+  sddmm_kernel<<<(unsigned)grid, 256, 0, st>>>(rp, col, m, w, P1, Q1, P2, Q2, dval);
+}
+
+}  // namespace frpca

@@ -1,0 +1,102 @@
+// Launchers of the gfx950 kernels (internal to the library; host-callable, enqueue only).
+#pragma once
+
+#include "common.h"
+
+namespace frpca {
+
+// ---------------------------------------------------------------- Gaussian test matrix
+// out[r*ld + j] = normal(seed, r*l + j) for j < l, 0 for l <= j < ld; FP32 and/or BF16.
+void launch_gaussian(uint64_t seed, int64_t rows, int l, int ld, float* out_f32,
+                     uint16_t* out_bf16, hipStream_t st);
+
+// ---------------------------------------------------------------- setup (create)
+// flag bits: 1 bad row_ptr ends, 2 decreasing row_ptr, 4 column out of range,
+// 8 columns not strictly increasing in a row, 16 non-finite value.
+void launch_validate_csr(int64_t m, int64_t n, int64_t nnz, const int64_t* row_ptr,
+                         const int32_t* col, const float* val, int* flag, hipStream_t st);
+void launch_ptr_to_i32(const int64_t* p, int64_t count, int32_t* out, hipStream_t st);
+void launch_expand_rows(const int32_t* rp, int64_t m, int64_t nnz, int32_t* row_of,
+                        hipStream_t st);
+// Exclusive scan of count int32 values: out[i] = sum(in[0..i)), out[count] = total.
+size_t scan_temp_bytes(int64_t count);
+void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t count, void* temp,
+                        hipStream_t st);
+// Stable LSD radix sort of (key, value) pairs on the low `bits` bits of the keys. The
+// sorted result ends in keys/vals (the *_alt arrays are scratch of the same size).
+size_t radix_temp_bytes(int64_t count);
+void radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
+                      int64_t count, int bits, void* temp, hipStream_t st);
+void launch_count_keys(const int32_t* keys, int64_t count, int32_t* counts, hipStream_t st);
+void launch_gather_csc(const uint32_t* perm, const int32_t* row_of, const float* val,
+                       int64_t nnz, int32_t* row_csc, float* val_csc, hipStream_t st);
+void launch_gather_values(const int32_t* perm, const float* val, int64_t nnz, float* out,
+                          hipStream_t st);
+
+// ---------------------------------------------------------------- merge-path products
+struct MergePlan {
+  const int32_t* ptr = nullptr;   // segment pointers [nseg+1]
+  const int32_t* idx = nullptr;   // gathered-row index per nonzero [nnz]
+  const float* val = nullptr;     // value per nonzero [nnz]
+  int64_t nseg = 0, nnz = 0;
+  int64_t nwaves = 0;             // number of merge-path partitions (one wave each)
+  int64_t ipw = 0;                // merge items (nonzeros + segment ends) per wave
+  int32_t* part_seg = nullptr;    // [nwaves+1] first segment of each partition
+  int32_t* part_e = nullptr;      // [nwaves+1] first nonzero of each partition
+  int32_t* fix_w0 = nullptr;      // [nwaves] first carrying wave of the segment whose
+                                  //   head ends in wave w, or -1
+  float* carry = nullptr;         // [nwaves*128] partial sums carried out of each wave
+  float* head = nullptr;          // [nwaves*128] partial sums of continued first segments
+};
+int64_t merge_items_per_wave(int64_t nseg, int64_t nnz);
+void launch_merge_partition(MergePlan& p, hipStream_t st);
+void launch_merge_fixplan(MergePlan& p, hipStream_t st);
+// out[seg, 0:lp) = sum_{e in seg} val[e] * in[idx[e], 0:lp)  (lp even, <= 128)
+void launch_spmm(const MergePlan& p, int lp, const void* in, bool in_bf16, int ld_in,
+                 float* out_f32, uint16_t* out_bf16, int ld_out, hipStream_t st);
+
+// ---------------------------------------------------------------- dense kernels
+// Gram G = X1^T X2 (l x l, FP64, ld = ldg) of tall panels (rows x l); symmetric when
+// X2 == nullptr (X2 = X1). partial: scratch of gram_partial_bytes().
+size_t gram_partial_bytes(int l);
+void launch_gram(const void* X1, bool bf16, int ld1, const float* X2, int ld2, int64_t rows,
+                 int l, double* partial, double* G, int ldg, hipStream_t st);
+// out[rows x c_out] = X[rows x kdim] B[kdim x c] (+ out if accumulate); columns c..c_out-1
+// written as 0. FP64 MFMA accumulation. out_bf16 (optional) receives a BF16 copy.
+void launch_tsmm(const void* X, bool x_bf16, int ldx, int64_t rows, int kdim, const double* B,
+                 int ldb, int c, int c_out, float* out, int ldo, uint16_t* out_bf16, int ldo16,
+                 bool accumulate, hipStream_t st);
+
+// Symmetric eigendecomposition by cyclic Jacobi (G: l x l FP64, ldg). d ascending, W l x l.
+size_t eig_log_bytes(int l);
+void launch_eig(const double* G, int ldg, int l, double* d, double* W, double* rotlog,
+                int* nsteps, int* order, double* diag_tmp, hipStream_t st);
+// eigSVD basis coefficients: B[a][j] = W[a][j] / sigma_j (0 if sigma_j <= tol*max), sigma out.
+void launch_eigsvd_coeffs(const double* d, const double* W, int l, int ldb, double tol,
+                          double* B, double* sigma, hipStream_t st);
+// Final Rayleigh-Ritz selection ind = l-1 .. l-k: S[i] = sigma_{l-1-i},
+// Blong[a][i] = W[a][l-1-i]/S[i], Bshort[a][i] = W[a][l-1-i]; dropped -> 0.
+void launch_final_coeffs(const double* d, const double* W, int l, int k, int ldb,
+                         double rank_tol, double* Blong, double* Bshort, float* S,
+                         int* ndropped, hipStream_t st);
+// Sign convention on V (rows x k, ld k): sign_i = sign of V's largest-|.| entry of column i.
+size_t sign_partial_bytes(int64_t rows, int k);
+// Blong (brows x ldb) gets the same column signs, so U = Z Blong inherits them.
+void launch_sign_fix(float* V, int64_t rows, int k, double* Blong, int ldb, int brows, void* partial,
+                     hipStream_t st);
+
+// LU basis (tournament pivoting) -> coefficient matrix B (l x l, FP64, ldb) with Q = X B.
+size_t lu_temp_bytes(int64_t rows, int l);
+void launch_lu_coeffs(const float* X, int ldx, int64_t rows, int l, double tol, double* B,
+                      int ldb, void* temp, int* ndropped_dev, hipStream_t st);
+
+// ---------------------------------------------------------------- adjoint
+// From J = U^T dU, K = V^T dV (k x k, FP64, ld k) and S, dS: coefficient matrices
+// CU = M - J S+, CV = -K S+, SP = diag(S+) (k x k, FP64, ld k).
+void launch_adjoint_small(const double* J, const double* K, const float* S, const float* dS,
+                          int k, bool has_du, bool has_dv, double* CU, double* CV, double* SP,
+                          hipStream_t st);
+void launch_sddmm(const int32_t* rp, const int32_t* col, int64_t m, int w, const float* P1,
+                  const float* Q1, const float* P2, const float* Q2, float* dval, hipStream_t st);
+
+}  // namespace frpca

@@ -1,0 +1,163 @@
+"""End-to-end parity of frPCA / frPCAt on the GPU against the FP64 oracle (same Gaussian draws).
+
+Tolerances: relative singular-value error <= 1e-4 and largest principal angle <= 1e-3 rad
+(sine) on the leading block separated by a relative Ritz gap >= 1e-2 (on the full k when
+the gap at k allows it).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import ANG_TOL, SIG_TOL, compare_triplets, np64, say
+from synth import aminer_tfidf, planted_blocks, random_sparse, small_decay, zipf_lognormal, zipf_normal
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1810_06825_amd import FrPCA, FrpcaError, binding  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def run_gpu(A, k, q, s, seed, **kw):
+    mat = FrPCA.from_csr(A, device=DEV, **kw)
+    U, S, V = mat.run(k, q, s, seed)
+    torch.cuda.synchronize()
+    info = mat.info()
+    out = np64(U), np64(S), np64(V), info
+    mat.close()
+    return out
+
+
+def check(A, k, q, s, seed, sig_tol=SIG_TOL, ang_tol=ANG_TOL, **kw):
+    say("frpca", A.meta.get("workload", "matrix"), A.m, A.n, A.nnz, f"k={k} q={q} s={s} seed={seed}", kw)
+    Ug, Sg, Vg, info = run_gpu(A, k, q, s, seed, **kw)
+    Uo, So, Vo, oinfo = oracle.frpca(A, k, q, s, seed)
+    S_ritz = oracle.frpca(A, k + 1, q, s - 1, seed)[1] if s >= 1 else None
+    r = compare_triplets(Uo, So, Vo, Ug, Sg, Vg, S_ritz, sig_tol, ang_tol)
+    say("  ->", {kk: (round(v, 8) if isinstance(v, float) else v) for kk, v in r.items()})
+    assert info["orientation"] == (6 if A.m >= A.n else 5)
+    return r, (Ug, Sg, Vg), (Uo, So, Vo), info
+
+
+def test_small_decay_workload():
+    # 2,000 x 1,000 at 1% density, k = 10, s = 5, three passes (the oracle-sized case)
+    r, *_ = check(small_decay(), 10, 3, 5, 20181015)
+    assert r["ok"] and r["prefix"] >= 8
+
+
+@pytest.mark.parametrize("q", [2, 3, 4, 5, 6, 7])
+def test_pass_counts_tall(q):
+    A = zipf_lognormal(m=30_011, n=4_003, t=40)
+    r, *_ = check(A, 20, q, 10, 1234 + q)
+    assert r["ok"], r
+
+
+@pytest.mark.parametrize("q", [2, 3, 4, 5])
+def test_pass_counts_wide_alg5(q):
+    A = zipf_normal(m=3_001, n=20_011, t=30)
+    r, *_ = check(A, 16, q, 8, 99 + q)
+    assert r["ok"], r
+
+
+def test_aminer_like_tfidf():
+    A = aminer_tfidf(m=80_000, n=20_000, t=20)
+    r, *_ = check(A, 50, 5, 20, 7)
+    assert r["ok"], r
+
+
+def test_planted_spectrum_closed_form():
+    P = planted_blocks(m=20_000, n=5_000, blocks=100)
+    k, s = 30, 10
+    r, (Ug, Sg, Vg), _, _ = check(P, k, 7, s, 3)
+    assert r["ok"], r
+    sig = P.meta["sigma"][:k]
+    assert np.all(Sg <= sig * (1 + 1e-5))        # Rayleigh-Ritz interlacing (FP32 slack)
+    assert np.max(np.abs(Sg[:10] - sig[:10]) / sig[:10]) < 1e-4
+
+
+@pytest.mark.parametrize("tall", [True, False])
+def test_exact_recovery_rank_below_k(tall):
+    P = planted_blocks(m=3000, n=1200, blocks=8, decades=1.0)
+    A = P if tall else oracle.transpose(P)
+    if not tall:
+        A.meta = {"workload": "planted_T"}
+        from synth.matrices import Csr
+        A = Csr(A.m, A.n, np.asarray(A.row_ptr, np.int64), np.asarray(A.col, np.int32),
+                np.asarray(A.val, np.float32), {"workload": "planted_T"})
+    k, s = 12, 6
+    say("exact recovery", tall)
+    Ug, Sg, Vg, info = run_gpu(A, k, 4, s, 5)
+    sig = P.meta["sigma"]
+    assert np.max(np.abs(Sg[:8] - sig) / sig) < 1e-5
+    assert np.all(Sg[8:] == 0) and info["rank_dropped"] == 4
+    assert np.all(Ug[:, 8:] == 0) and np.all(Vg[:, 8:] == 0)
+
+
+def test_full_subspace_is_exact_svd():
+    A = random_sparse(300, 90, 0.2, seed=4)
+    k, s = 60, 30  # l = n: the sketch spans the whole row space
+    say("full subspace")
+    Ug, Sg, Vg, _ = run_gpu(A, k, 3, s, 9)
+    sref = np.linalg.svd(A.toarray(), compute_uv=False)[:k]
+    assert np.max(np.abs(Sg - sref) / sref) < 1e-4
+
+
+def test_bf16_panel_variant_error_stated():
+    A = zipf_lognormal(m=30_011, n=4_003, t=40)
+    say("bf16 panels")
+    r, *_ = check(A, 20, 5, 10, 77, sig_tol=1.0, ang_tol=1.0, panel_bf16=True)
+    say("  bf16 panel error vs FP64 oracle:", r)
+    assert r["sig_err"] < 1e-2
+
+
+def test_determinism_bitwise():
+    A = zipf_lognormal(m=20_000, n=3_000, t=40)
+    say("determinism")
+    a = run_gpu(A, 20, 5, 10, 5)
+    b = run_gpu(A, 20, 5, 10, 5)
+    for x, y in zip(a[:3], b[:3]):
+        assert np.array_equal(x, y)
+
+
+def test_sign_convention_applied():
+    A = zipf_lognormal(m=10_000, n=2_000, t=40)
+    Ug, Sg, Vg, _ = run_gpu(A, 10, 4, 5, 1)
+    for i in range(10):
+        j = np.argmax(np.abs(Vg[:, i]))
+        assert Vg[j, i] > 0
+
+
+def test_argument_errors():
+    A = random_sparse(100, 50, 0.1, seed=1)
+    mat = FrPCA.from_csr(A, device=DEV)
+    for args in ((5, 1, 3, 1), (30, 3, 30, 1), (0, 3, 2, 1), (100, 3, 40, 1)):
+        with pytest.raises(FrpcaError) as ei:
+            mat.run(*args)
+        assert ei.value.code == binding.FRPCA_EINVAL
+    mat.close()
+
+
+@pytest.mark.parametrize("bad", ["unsorted", "range", "nan", "rowptr"])
+def test_malformed_csr_rejected(bad):
+    A = random_sparse(60, 40, 0.2, seed=2)
+    rp, col, val = A.row_ptr.copy(), A.col.copy(), A.val.copy()
+    r = int(np.argmax(np.diff(rp) >= 2))
+    if bad == "unsorted":
+        col[rp[r]], col[rp[r] + 1] = col[rp[r] + 1], col[rp[r]]
+    elif bad == "range":
+        col[-1] = 40
+    elif bad == "nan":
+        val[3] = np.nan
+    else:
+        rp[-1] += 1
+    t = lambda a: torch.from_numpy(a).to(DEV)  # noqa: E731
+    with pytest.raises(FrpcaError) as ei:
+        FrPCA(t(rp), t(col), t(val), (A.m, A.n))
+    assert ei.value.code == binding.FRPCA_EINVAL
+
+
+def test_empty_matrix_values_give_zero_outputs():
+    A = random_sparse(200, 100, 0.0, seed=1)
+    Ug, Sg, Vg, info = run_gpu(A, 5, 3, 2, 1)
+    assert np.all(Sg == 0) and np.all(Ug == 0) and np.all(Vg == 0)
