@@ -4,8 +4,8 @@
 //
 // Each MFMA multiplies a 16x4 tile of X^T by a 4x16 tile of X: lane l supplies
 // X[r0 + l/16][16*I + l%16] as the A operand (tile row I) and the same formula with J as the
-// B operand; the 16x16 result tile is held 4 values per lane (rows 4*(l/16)..+3, column
-// l%16). The l x l output is covered by NT x NT tiles (NT = ceil(l/16) rounded to even);
+// B operand; the 16x16 result tile is held 4 values per lane: value q of lane l is row
+// l/16 + 4q, column l%16 (layout checked on gfx950). The l x l output is covered by NT x NT tiles (NT = ceil(l/16) rounded to even);
 // for the symmetric Gram only the NT(NT+1)/2 upper tiles are computed. The four waves of a
 // block split the tiles and walk the same rows 4 at a time. Each block writes its partial
 // tiles; a second kernel adds the partials of all blocks in block order (deterministic).
@@ -122,7 +122,7 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(const double* partial,
     I = p / nt;
     J = p % nt;
   }
-  const int i = 16 * I + 4 * (lane >> 4) + r;
+  const int i = 16 * I + (lane >> 4) + 4 * r;
   const int j = 16 * J + (lane & 15);
   if (i >= l || j >= l) return;
   if (sym) {

@@ -5,8 +5,8 @@
 // U = Z W(:,ind) diag(1/S(ind)) and V = Q W(:,ind) of Alg. 5/6, and the adjoint's panels.
 // B (<= 128 x 128, FP64) sits in LDS; a wave computes a 16-row strip of out as NCT 16x16
 // tiles with v_mfma_f64_16x16x4f64: lane l supplies X[r0 + l%16][4t + l/16] as the A operand
-// and B[4t + l/16][16j + l%16] as the B operand of k-step t, and holds result rows
-// 4*(l/16)..+3 of column l%16. FP32 (or BF16) inputs are widened exactly to FP64.
+// and B[4t + l/16][16j + l%16] as the B operand of k-step t; value q of its result is row
+// l/16 + 4q, column l%16 (layout checked on gfx950). FP32 (or BF16) inputs are widened exactly to FP64.
 #include "kernels.h"
 
 namespace frpca {
@@ -69,7 +69,7 @@ __global__ __launch_bounds__(256) void tsmm_kernel(TsmmArgs a) {
       const int col = 16 * j + lr;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int64_t row = r0 + 4 * lk + q;
+        const int64_t row = r0 + lk + 4 * q;
         if (row < a.rows && col < a.c_out) {
           float v = (col < a.c) ? (float)acc[j][q] : 0.0f;
           if (a.out) {
