@@ -43,7 +43,8 @@ extern "C" {
 #define FRPCA_T_SIGN 7    /* output sign convention                                   */
 #define FRPCA_T_BWD 8     /* adjoint: cross-Gram, k x k terms, panels                  */
 #define FRPCA_T_SDDMM 9   /* adjoint projected onto the sparsity pattern              */
-#define FRPCA_NTIMERS 10
+#define FRPCA_T_SPMM_FIX 10 /* merge-path carry fix-up of both products               */
+#define FRPCA_NTIMERS 11
 
 typedef struct frpca_ctx* frpca_t;
 

@@ -17,8 +17,9 @@ FRPCA_EINVAL = -1
 FRPCA_ENOMEM = -2
 FRPCA_EHIP = -3
 FRPCA_ESTATE = -4
-NTIMERS = 10
-TIMER_NAMES = ("gauss", "spmm_fwd", "spmm_back", "gram", "eig", "lu", "tsmm", "sign", "bwd", "sddmm")
+NTIMERS = 11
+TIMER_NAMES = ("gauss", "spmm_fwd", "spmm_back", "gram", "eig", "lu", "tsmm", "sign", "bwd", "sddmm",
+               "spmm_fixup")
 
 
 class FrpcaError(RuntimeError):

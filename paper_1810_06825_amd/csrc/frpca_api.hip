@@ -407,15 +407,22 @@ int frpca_run(frpca_t h, int k, int p_passes, int s_oversample, uint64_t seed, f
     const int64_t Ns = h->short_rows(), Nl = h->long_rows();
     const int fwd_cls = FRPCA_T_SPMM_F, back_cls = FRPCA_T_SPMM_B;
 
+    // one product = main merge-path kernel + carry fix-up, timed as separate classes
+    auto spmm = [&](const MergePlan& p, int cls, const void* in, bool in_b, float* o32, uint16_t* o16) {
+      {
+        frpca_ctx::Scope t(h, cls);
+        launch_spmm_main(p, LP, in, in_b, LP, o32, o16, LP, st);
+      }
+      frpca_ctx::Scope t(h, FRPCA_T_SPMM_FIX);
+      launch_spmm_fixup(p, LP, o32, o16, LP, st);
+    };
     auto forward_inner = [&] {
-      frpca_ctx::Scope t(h, fwd_cls);
-      if (bf) launch_spmm(Fp, LP, h->Qb, true, LP, nullptr, h->Yb, LP, st);
-      else launch_spmm(Fp, LP, h->Q, false, LP, h->Y, nullptr, LP, st);
+      if (bf) spmm(Fp, fwd_cls, h->Qb, true, nullptr, h->Yb);
+      else spmm(Fp, fwd_cls, h->Q, false, h->Y, nullptr);
     };
     auto back = [&] {
-      frpca_ctx::Scope t(h, back_cls);
-      if (bf) launch_spmm(Bp, LP, h->Yb, true, LP, h->X, nullptr, LP, st);
-      else launch_spmm(Bp, LP, h->Y, false, LP, h->X, nullptr, LP, st);
+      if (bf) spmm(Bp, back_cls, h->Yb, true, h->X, nullptr);
+      else spmm(Bp, back_cls, h->Y, false, h->X, nullptr);
     };
     auto basis_from_B1 = [&] {
       frpca_ctx::Scope t(h, FRPCA_T_TSMM);
@@ -463,10 +470,7 @@ int frpca_run(frpca_t h, int k, int p_passes, int s_oversample, uint64_t seed, f
       else orth_lu();
     }
     // final pass and Rayleigh-Ritz: eigSVD of the long-side panel Z
-    {
-      frpca_ctx::Scope t(h, fwd_cls);
-      launch_spmm(Fp, LP, h->Q, false, LP, h->Z, nullptr, LP, st);
-    }
+    spmm(Fp, fwd_cls, h->Q, false, h->Z, nullptr);
     gram_eig(h->Z, Nl);
     launch_final_coeffs(h->d, h->W, l, k, LP, h->rank_tol, h->B1, h->B2, S, h->ndrop, st);
     // B1 multiplies the long-side panel Z, B2 the short-side basis Q

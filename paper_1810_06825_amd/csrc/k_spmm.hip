@@ -127,16 +127,27 @@ __global__ __launch_bounds__(256) void spmm_fixup_kernel(const int32_t* part_seg
 
 }  // namespace
 
-void launch_spmm(const MergePlan& p, int lp, const void* in, bool in_bf16, int ld_in, float* out_f32,
-                 uint16_t* out_bf16, int ld_out, hipStream_t st) {
+void launch_spmm_main(const MergePlan& p, int lp, const void* in, bool in_bf16, int ld_in, float* out_f32,
+                      uint16_t* out_bf16, int ld_out, hipStream_t st) {
   if (p.nwaves <= 0) return;
   SpmmArgs a{p.ptr, p.idx, p.val, p.part_seg, p.part_e, p.nseg, p.nwaves, in, ld_in, out_f32, out_bf16,
              ld_out, lp, p.carry, p.head};
   const unsigned grid = (unsigned)((p.nwaves + 3) / 4);
   if (in_bf16) spmm_merge_kernel<true><<<grid, 256, 0, st>>>(a);
   else spmm_merge_kernel<false><<<grid, 256, 0, st>>>(a);
+}
+
+void launch_spmm_fixup(const MergePlan& p, int lp, float* out_f32, uint16_t* out_bf16, int ld_out, hipStream_t st) {
+  if (p.nwaves <= 0) return;
+  const unsigned grid = (unsigned)((p.nwaves + 3) / 4);
   spmm_fixup_kernel<<<grid, 256, 0, st>>>(p.part_seg, p.fix_w0, p.nwaves, p.carry, p.head, out_f32, out_bf16,
                                           ld_out, lp);
+}
+
+void launch_spmm(const MergePlan& p, int lp, const void* in, bool in_bf16, int ld_in, float* out_f32,
+                 uint16_t* out_bf16, int ld_out, hipStream_t st) {
+  launch_spmm_main(p, lp, in, in_bf16, ld_in, out_f32, out_bf16, ld_out, st);
+  launch_spmm_fixup(p, lp, out_f32, out_bf16, ld_out, st);
 }
 
 }  // namespace frpca

@@ -51,7 +51,13 @@ struct MergePlan {
 int64_t merge_items_per_wave(int64_t nseg, int64_t nnz);
 void launch_merge_partition(MergePlan& p, hipStream_t st);
 void launch_merge_fixplan(MergePlan& p, hipStream_t st);
-// out[seg, 0:lp) = sum_{e in seg} val[e] * in[idx[e], 0:lp)  (lp even, <= 128)
+// out[seg, 0:lp) = sum_{e in seg} val[e] * in[idx[e], 0:lp)  (lp even, <= 128):
+// launch_spmm_main writes every segment that ends inside one partition and the carries of
+// cut segments; launch_spmm_fixup then completes the cut segments. launch_spmm does both.
+void launch_spmm_main(const MergePlan& p, int lp, const void* in, bool in_bf16, int ld_in,
+                      float* out_f32, uint16_t* out_bf16, int ld_out, hipStream_t st);
+void launch_spmm_fixup(const MergePlan& p, int lp, float* out_f32, uint16_t* out_bf16,
+                       int ld_out, hipStream_t st);
 void launch_spmm(const MergePlan& p, int lp, const void* in, bool in_bf16, int ld_in,
                  float* out_f32, uint16_t* out_bf16, int ld_out, hipStream_t st);
 
