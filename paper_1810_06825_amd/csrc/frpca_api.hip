@@ -334,8 +334,8 @@ int frpca_create(frpca_t* out, int64_t m, int64_t n, int64_t nnz, const int64_t*
     {
       // stable sort of CSR positions by column gives the column-major order
       const size_t nb = std::max<int64_t>(nnz, 1) * sizeof(uint32_t);
-      DeviceTemp keys(nb), keys_alt(nb), vals_alt(nb), row_of(nb), counts((n + 1) * sizeof(int32_t));
-      DeviceTemp rtmp(radix_temp_bytes(nnz)), stmp(scan_temp_bytes(n));
+      DeviceTemp keys(nb), keys_alt(nb), vals_alt(nb), row_of(nb);
+      DeviceTemp rtmp(radix_temp_bytes(nnz));
       uint32_t* kk = static_cast<uint32_t*>(keys.p);
       uint32_t* vv = reinterpret_cast<uint32_t*>(h->perm);
       if (nnz > 0) {
@@ -344,9 +344,7 @@ int frpca_create(frpca_t* out, int64_t m, int64_t n, int64_t nnz, const int64_t*
         radix_sort_pairs(kk, vv, static_cast<uint32_t*>(keys_alt.p), static_cast<uint32_t*>(vals_alt.p), nnz,
                          bits_for(n - 1), rtmp.p, st);
       }
-      FRPCA_HIP(hipMemsetAsync(counts.p, 0, (n + 1) * sizeof(int32_t), st));
-      launch_count_keys(col, nnz, static_cast<int32_t*>(counts.p), st);
-      exclusive_scan_i32(static_cast<int32_t*>(counts.p), h->cp32, n, stmp.p, st);
+      launch_ptr_from_sorted(kk, nnz, n, h->cp32, st);
       launch_expand_rows(h->rp32, m, nnz, static_cast<int32_t*>(row_of.p), st);
       launch_gather_csc(vv, static_cast<int32_t*>(row_of.p), val, nnz, h->row_csc, h->val_csc, st);
       check_launch();

@@ -181,9 +181,16 @@ __global__ __launch_bounds__(kWave) void radix_scatter_kernel(const uint32_t* ke
   }
 }
 
-__global__ __launch_bounds__(256) void count_keys_kernel(const int32_t* keys, int64_t count, int32_t* counts) {
+// Segment pointers from keys sorted ascending: ptr[c] = first position whose key is >= c.
+// Thread i owns the boundary between positions i-1 and i and fills the pointers of every
+// key value in (key[i-1], key[i]]; no atomics, so power-law heads cost nothing extra.
+__global__ __launch_bounds__(256) void ptr_from_sorted_kernel(const uint32_t* keys, int64_t count, int64_t nseg,
+                                                              int32_t* ptr) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < count) atomicAdd(&counts[keys[i]], 1);
+  if (i > count) return;
+  const int64_t lo = (i == 0) ? 0 : (int64_t)keys[i - 1] + 1;
+  const int64_t hi = (i == count) ? nseg : (int64_t)keys[i];
+  for (int64_t c = lo; c <= hi; ++c) ptr[c] = (int32_t)i;
 }
 
 __global__ __launch_bounds__(256) void gather_csc_kernel(const uint32_t* perm, const int32_t* row_of,
@@ -320,8 +327,8 @@ void radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32
   }
 }
 
-void launch_count_keys(const int32_t* keys, int64_t count, int32_t* counts, hipStream_t st) {
-  if (count > 0) count_keys_kernel<<<grid_for(count, 256), 256, 0, st>>>(keys, count, counts);
+void launch_ptr_from_sorted(const uint32_t* keys, int64_t count, int64_t nseg, int32_t* ptr, hipStream_t st) {
+  ptr_from_sorted_kernel<<<grid_for(count + 1, 256), 256, 0, st>>>(keys, count, nseg, ptr);
 }
 
 void launch_gather_csc(const uint32_t* perm, const int32_t* row_of, const float* val, int64_t nnz,

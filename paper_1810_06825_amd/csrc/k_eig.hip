@@ -46,14 +46,22 @@ __global__ __launch_bounds__(kEigThreads) void jacobi_kernel(const double* G, in
   __shared__ double A[kMaxN * (kMaxN + 1) / 2];
   __shared__ double rc[kMaxN / 2], rs[kMaxN / 2];
   __shared__ int rflag[kMaxN / 2];
+  __shared__ unsigned short pairs[(kMaxN - 1) * (kMaxN / 2)];  // p | q << 8 for (round, slot)
+  __shared__ int rowbase[kMaxN];                               // packed(a, b) = rowbase[a] + b, a <= b
   __shared__ unsigned char blk_i[kMaxN / 2 * (kMaxN / 2 - 1) / 2], blk_j[kMaxN / 2 * (kMaxN / 2 - 1) / 2];
   __shared__ int any_rot;
   const int N = l + (l & 1);  // an odd size gets a zero dummy index that never rotates
   const int half = N / 2;
   const int tid = threadIdx.x;
+  for (int a = tid; a < N; a += kEigThreads) rowbase[a] = a * N - (a * (a - 1)) / 2 - a;
   for (int i = 0; i < N; ++i)
     for (int j = i + tid; j < N; j += kEigThreads)
       A[packed(i, j, N)] = (i < l && j < l) ? G[(size_t)i * ldg + j] : 0.0;
+  for (int e = tid; e < (N - 1) * half; e += kEigThreads) {
+    int p, q;
+    rr_pair(e / half, e % half, N, p, q);
+    pairs[e] = (unsigned short)(p | (q << 8));
+  }
   const int nblk = half * (half - 1) / 2;
   for (int b = tid; b < nblk; b += kEigThreads) {
     int i = 0, r = b;
@@ -65,15 +73,17 @@ __global__ __launch_bounds__(kEigThreads) void jacobi_kernel(const double* G, in
     blk_j[b] = (unsigned char)(i + 1 + r);
   }
   __syncthreads();
+  auto pk = [&](int a, int b) { return a <= b ? rowbase[a] + b : rowbase[b] + a; };
   int step = 0;
   for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
     if (tid == 0) any_rot = 0;
     __syncthreads();
     for (int s = 0; s < N - 1; ++s, ++step) {
+      const unsigned short* pr = pairs + s * half;
       if (tid < half) {
-        int p, q;
-        rr_pair(s, tid, N, p, q);
-        const double app = A[packed(p, p, N)], aqq = A[packed(q, q, N)], apq = A[packed(p, q, N)];
+        const int p = pr[tid] & 255, q = pr[tid] >> 8;
+        const int ipp = rowbase[p] + p, iqq = rowbase[q] + q, ipq = rowbase[p] + q;
+        const double app = A[ipp], aqq = A[iqq], apq = A[ipq];
         double c = 1.0, sn = 0.0;
         int f = 0;
         if (apq != 0.0 && fabs(apq) > kJacobiTol * sqrt(fabs(app * aqq))) {
@@ -81,9 +91,9 @@ __global__ __launch_bounds__(kEigThreads) void jacobi_kernel(const double* G, in
           const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
           c = 1.0 / sqrt(1.0 + t * t);
           sn = t * c;
-          A[packed(p, p, N)] = app - t * apq;
-          A[packed(q, q, N)] = aqq + t * apq;
-          A[packed(p, q, N)] = 0.0;
+          A[ipp] = app - t * apq;
+          A[iqq] = aqq + t * apq;
+          A[ipq] = 0.0;
           f = 1;
           any_rot = 1;
         }
@@ -97,11 +107,9 @@ __global__ __launch_bounds__(kEigThreads) void jacobi_kernel(const double* G, in
       for (int b = tid; b < nblk; b += kEigThreads) {
         const int i = blk_i[b], j = blk_j[b];
         if (!(rflag[i] | rflag[j])) continue;
-        int p, q, r, t;
-        rr_pair(s, i, N, p, q);
-        rr_pair(s, j, N, r, t);
+        const int p = pr[i] & 255, q = pr[i] >> 8, r = pr[j] & 255, t = pr[j] >> 8;
         const double ci = rc[i], si = rs[i], cj = rc[j], sj = rs[j];
-        const int ipr = pidx(p, r, N), ipt = pidx(p, t, N), iqr = pidx(q, r, N), iqt = pidx(q, t, N);
+        const int ipr = pk(p, r), ipt = pk(p, t), iqr = pk(q, r), iqt = pk(q, t);
         const double gpr = A[ipr], gpt = A[ipt], gqr = A[iqr], gqt = A[iqt];
         // rows: (J_i^T G)
         const double xr = ci * gpr - si * gqr, yr = si * gpr + ci * gqr;
@@ -118,7 +126,7 @@ __global__ __launch_bounds__(kEigThreads) void jacobi_kernel(const double* G, in
     __syncthreads();
   }
   if (tid == 0) *nsteps = step;
-  for (int i = tid; i < l; i += kEigThreads) diag_out[i] = A[packed(i, i, N)];
+  for (int i = tid; i < l; i += kEigThreads) diag_out[i] = A[rowbase[i] + i];
 }
 
 // Eigenvalues in ascending order (ties by index) and the rank of each original index.
@@ -135,43 +143,78 @@ __global__ __launch_bounds__(128) void eig_sort_kernel(const double* diag, int l
   d[r] = v;
 }
 
-// Row `blockIdx.x` of the eigenvector matrix: e_r^T J_1 J_2 ... J_T, replayed from the log.
+// Row `blockIdx.x` of the eigenvector matrix: e_r^T J_1 J_2 ... J_T, replayed from the log
+// by one wave with the row in registers. Lane i holds the two entries of round-robin slot i
+// (indices ia, ib). From one round to the next every index of slot i >= 1 advances by one
+// (mod N-1) and slot 0 keeps N-1, which moves the values between neighbouring lanes:
+// a-values shift down one lane (the last slot takes its own b-value), b-values shift up one
+// lane (slot 1 takes slot 0's b, slot 0 takes slot 1's a).
 __global__ __launch_bounds__(64) void eigvec_kernel(const double* rotlog, const int* nsteps, int l, const int* rank,
                                                     double* W) {
-  __shared__ double v[kMaxN];
   const int r = blockIdx.x;
   const int lane = threadIdx.x;
   const int N = l + (l & 1), half = N / 2;
-  for (int c = lane; c < N; c += 64) v[c] = (c == r) ? 1.0 : 0.0;
-  __syncthreads();
+  const bool live = lane < half;
+  int ia, ib;
+  if (lane == 0) {
+    ia = N - 1;
+    ib = 0;
+  } else {
+    ia = lane;
+    ib = N - 1 - lane;
+  }
+  double va = (ia == r) ? 1.0 : 0.0, vb = (ib == r) ? 1.0 : 0.0;
   const int T = *nsteps;
   constexpr int kPre = 8;
-  double cb[kPre], sb[kPre];
-  for (int st0 = 0; st0 < T; st0 += kPre) {
+  double cb[kPre], sb[kPre], cn[kPre], sn[kPre];
+  auto fetch = [&](int st0, double* c, double* s) {
 #pragma unroll
     for (int u = 0; u < kPre; ++u) {
-      cb[u] = 1.0;
-      sb[u] = 0.0;
-      if (lane < half && st0 + u < T) {
-        cb[u] = rotlog[((size_t)(st0 + u) * (kMaxN / 2) + lane) * 2 + 0];
-        sb[u] = rotlog[((size_t)(st0 + u) * (kMaxN / 2) + lane) * 2 + 1];
+      c[u] = 1.0;
+      s[u] = 0.0;
+      if (live && st0 + u < T) {
+        c[u] = rotlog[((size_t)(st0 + u) * (kMaxN / 2) + lane) * 2 + 0];
+        s[u] = rotlog[((size_t)(st0 + u) * (kMaxN / 2) + lane) * 2 + 1];
       }
     }
+  };
+  fetch(0, cb, sb);
+  const int up = min(lane + 1, 63), dn = max(lane - 1, 0);
+  for (int st0 = 0; st0 < T; st0 += kPre) {
+    fetch(st0 + kPre, cn, sn);  // next batch in flight while this one is applied
 #pragma unroll
     for (int u = 0; u < kPre; ++u) {
       if (st0 + u < T) {
-        if (lane < half && sb[u] != 0.0) {
-          int p, q;
-          rr_pair((st0 + u) % (N - 1), lane, N, p, q);
-          const double vp = v[p], vq = v[q];
-          v[p] = cb[u] * vp - sb[u] * vq;
-          v[q] = sb[u] * vp + cb[u] * vq;
+        if (sb[u] != 0.0) {
+          // the logged rotation is for (p, q) = (min, max) of the slot's indices
+          const bool aq = ia < ib;
+          const double vp = aq ? va : vb, vq = aq ? vb : va;
+          const double np = cb[u] * vp - sb[u] * vq, nq = sb[u] * vp + cb[u] * vq;
+          va = aq ? np : nq;
+          vb = aq ? nq : np;
         }
-        __syncthreads();
+        if (half > 1) {  // with a single pair nothing moves
+          const double t1 = __shfl(va, up);
+          const double t2 = __shfl(vb, dn);
+          const double na = (lane == 0) ? va : (lane == half - 1 ? vb : t1);
+          const double nb = (lane == 0) ? t1 : t2;
+          va = na;
+          vb = nb;
+        }
+        if (lane != 0) ia = (ia + 1 == N - 1) ? 0 : ia + 1;
+        ib = (ib + 1 == N - 1) ? 0 : ib + 1;
       }
     }
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) {
+      cb[u] = cn[u];
+      sb[u] = sn[u];
+    }
   }
-  for (int c = lane; c < l; c += 64) W[(size_t)r * l + rank[c]] = v[c];
+  if (live) {
+    if (ia < l) W[(size_t)r * l + rank[ia]] = va;
+    if (ib < l) W[(size_t)r * l + rank[ib]] = vb;
+  }
 }
 
 // eigSVD basis coefficients (Alg. 2 steps 3-5): B = W diag(1/sigma), sigma = sqrt(max(d,0)),
@@ -228,7 +271,7 @@ __global__ __launch_bounds__(256) void final_coeffs_kernel(const double* d, cons
 
 // Sign convention: per column i of V (rows x k, ld k), the largest |entry| (ties: lowest
 // row). Pass 1: one partial (|v|, row) per block and column; pass 2 reduces in block order.
-constexpr int kSignRows = 2048;
+constexpr int kSignRows = 256;
 
 __global__ __launch_bounds__(256) void sign_partial_kernel(const float* V, int64_t rows, int k, float* pv, int* pr) {
   const int64_t r0 = (int64_t)blockIdx.x * kSignRows;

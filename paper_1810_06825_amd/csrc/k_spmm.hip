@@ -5,8 +5,8 @@
 // A^T Y, so the transpose product needs no atomics. Work is split by merge path (Merrill &
 // Garland, SC'16): each wave owns an equal share of (nonzeros + segment ends), which keeps
 // power-law columns with millions of entries balanced. A lane owns two panel columns
-// (float2), so a wave streams one 2*64-wide panel row per nonzero; the nonzero indices and
-// values are wave-uniform scalar loads. Partial sums of segments cut by a partition
+// (float2), so a wave streams one 2*64-wide panel row per nonzero; the (index, value)
+// stream is read 64 entries per coalesced load and broadcast with readlane. Partial sums of segments cut by a partition
 // boundary go to per-wave carry/head slots and a fix-up kernel adds them in wave order,
 // so results are deterministic.
 #include <climits>
@@ -33,12 +33,19 @@ struct SpmmArgs {
   float* head;
 };
 
-constexpr int kBatch = 8;
+constexpr int kBatch = 8;  // gathers in flight per wave
+
+// The sparse operand is read exactly once per product: non-temporal loads keep it from
+// displacing the gathered panel rows in the caches.
+template <class T>
+__device__ __forceinline__ T stream_load(const T* p) {
+  return __builtin_nontemporal_load(p);
+}
 
 template <bool IN_BF16>
 __global__ __launch_bounds__(256) void spmm_merge_kernel(SpmmArgs a) {
   const int lane = threadIdx.x & 63;
-  // wave index made explicitly uniform so the index/value stream uses scalar loads
+  // wave index made explicitly uniform so the partition bounds are scalar values
   const int64_t w = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (w >= a.nwaves) return;
   const int col = 2 * lane;
@@ -68,32 +75,53 @@ __global__ __launch_bounds__(256) void spmm_merge_kernel(SpmmArgs a) {
     next_end = (seg < seg_stop) ? a.ptr[seg + 1] : INT_MAX;
   };
 
+  // The (index, value) stream is read 64 entries at a time with one coalesced (streaming)
+  // load per wave; entries are broadcast with readlane, the next window is in flight while
+  // the current one is consumed.
+  int wbase = e;
+  int widx = 0, nidx = 0;
+  float wval = 0.f, nval = 0.f;
+  if (wbase + lane < e_stop) {
+    widx = stream_load(a.idx + wbase + lane);
+    wval = stream_load(a.val + wbase + lane);
+  }
   while (e < e_stop) {
-    const int nb = min(kBatch, e_stop - e);
-    int c[kBatch];
-    float v[kBatch];
-    float2 x[kBatch];
+    const int wend = min(wbase + 64, e_stop);
+    if (wbase + 64 + lane < e_stop) {
+      nidx = stream_load(a.idx + wbase + 64 + lane);
+      nval = stream_load(a.val + wbase + 64 + lane);
+    }
+    while (e < wend) {
+      const int nb = min(kBatch, wend - e);
+      const int off = e - wbase;
+      int c[kBatch];
+      float v[kBatch];
+      float2 x[kBatch];
 #pragma unroll
-    for (int t = 0; t < kBatch; ++t) {
-      if (t < nb) {
-        c[t] = a.idx[e + t];
-        v[t] = a.val[e + t];
+      for (int t = 0; t < kBatch; ++t) {
+        if (t < nb) {
+          c[t] = __builtin_amdgcn_readlane(widx, off + t);
+          v[t] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wval), off + t));
+        }
       }
-    }
 #pragma unroll
-    for (int t = 0; t < kBatch; ++t) {
-      x[t] = make_float2(0.f, 0.f);
-      if (t < nb && act) x[t] = load2<IN_BF16>(a.in, (size_t)c[t] * a.ld_in + col);
-    }
-#pragma unroll
-    for (int t = 0; t < kBatch; ++t) {
-      if (t < nb) {
-        while (next_end <= e + t) emit();
-        acc.x = fmaf(v[t], x[t].x, acc.x);
-        acc.y = fmaf(v[t], x[t].y, acc.y);
+      for (int t = 0; t < kBatch; ++t) {
+        x[t] = make_float2(0.f, 0.f);
+        if (t < nb && act) x[t] = load2<IN_BF16>(a.in, (size_t)c[t] * a.ld_in + col);
       }
+#pragma unroll
+      for (int t = 0; t < kBatch; ++t) {
+        if (t < nb) {
+          while (next_end <= e + t) emit();
+          acc.x = fmaf(v[t], x[t].x, acc.x);
+          acc.y = fmaf(v[t], x[t].y, acc.y);
+        }
+      }
+      e += nb;
     }
-    e += nb;
+    wbase += 64;
+    widx = nidx;
+    wval = nval;
   }
   while (seg < seg_stop) emit();
   if (seg_stop < a.nseg && act) store2_f32(a.carry, (size_t)w * 128 + col, acc);

@@ -27,7 +27,9 @@ void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t count, void* te
 size_t radix_temp_bytes(int64_t count);
 void radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
                       int64_t count, int bits, void* temp, hipStream_t st);
-void launch_count_keys(const int32_t* keys, int64_t count, int32_t* counts, hipStream_t st);
+// ptr[0..nseg]: ptr[c] = first position of keys (sorted ascending, values < nseg) >= c.
+void launch_ptr_from_sorted(const uint32_t* keys, int64_t count, int64_t nseg, int32_t* ptr,
+                            hipStream_t st);
 void launch_gather_csc(const uint32_t* perm, const int32_t* row_of, const float* val,
                        int64_t nnz, int32_t* row_csc, float* val_csc, hipStream_t st);
 void launch_gather_values(const int32_t* perm, const float* val, int64_t nnz, float* out,
