@@ -94,7 +94,7 @@ struct frpca_ctx {
   int ws_bf16 = -1;
   float *Q = nullptr, *X = nullptr, *Y = nullptr, *Z = nullptr;
   uint16_t *Qb = nullptr, *Yb = nullptr;
-  double *gram_part = nullptr, *G = nullptr, *W = nullptr, *d = nullptr, *diag = nullptr, *rotlog = nullptr;
+  double *gram_part = nullptr, *G = nullptr, *W = nullptr, *d = nullptr, *diag = nullptr;
   double *B1 = nullptr, *B2 = nullptr;
   int *order = nullptr, *nsteps = nullptr, *ndrop = nullptr;
   void *lu_tmp = nullptr, *sign_tmp = nullptr;
@@ -230,7 +230,6 @@ struct frpca_ctx {
       order = a.take<int>(kMaxL);
       nsteps = a.take<int>(4);
       ndrop = a.take<int>(4);
-      rotlog = a.take<double>(eig_log_bytes(lp) / sizeof(double));
       lu_tmp = a.take<char>(lu_temp_bytes(Ns, lp));
       sign_tmp = a.take<char>(sign_partial_bytes(Nl, kMaxL));
     };
@@ -439,7 +438,7 @@ int frpca_run(frpca_t h, int k, int p_passes, int s_oversample, uint64_t seed, f
         launch_gram(P, false, LP, nullptr, 0, rows, l, h->gram_part, h->G, l, st);
       }
       frpca_ctx::Scope t(h, FRPCA_T_EIG);
-      launch_eig(h->G, l, l, h->d, h->W, h->rotlog, h->nsteps, h->order, h->diag, st);
+      launch_eig(h->G, l, l, h->d, h->W, h->nsteps, st);
     };
     auto orth_eig = [&] {
       gram_eig(h->X, Ns);
@@ -570,10 +569,12 @@ int frpca_get_info(frpca_t h, frpca_info* info) {
     FRPCA_CHECK(info != nullptr, FRPCA_EINVAL, "NULL info");
     h->collect_timers();
     if (h->ws) {
-      int nd = 0;
+      int nd = 0, sw = 0;
       FRPCA_HIP(hipMemcpyAsync(&nd, h->ndrop, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+      FRPCA_HIP(hipMemcpyAsync(&sw, h->nsteps, sizeof(int), hipMemcpyDeviceToHost, h->stream));
       FRPCA_HIP(hipStreamSynchronize(h->stream));
       h->info.rank_dropped = nd;
+      h->info.eig_sweeps = sw;
     }
     h->info.workspace_bytes = h->setup_bytes + h->ws_bytes + h->bws_bytes;
     *info = h->info;
@@ -641,11 +642,8 @@ int frpca_eig(frpca_t h, int l, const double* G, double* W, double* d) {
   if (!h) return fail(nullptr, Error{FRPCA_EINVAL, "NULL handle"});
   return guarded(h, [&] {
     FRPCA_CHECK(l >= 1 && l <= kMaxL && G && W && d, FRPCA_EINVAL, "bad eig arguments");
-    DeviceTemp rot(eig_log_bytes(l)), misc(4096);
-    int* nsteps = static_cast<int*>(misc.p);
-    int* order = nsteps + 64;
-    double* diag = reinterpret_cast<double*>(static_cast<char*>(misc.p) + 2048);
-    launch_eig(G, l, l, d, W, static_cast<double*>(rot.p), nsteps, order, diag, h->stream);
+    DeviceTemp misc(256);
+    launch_eig(G, l, l, d, W, static_cast<int*>(misc.p), h->stream);
     check_launch();
     FRPCA_HIP(hipStreamSynchronize(h->stream));
   });
@@ -658,17 +656,16 @@ int frpca_eigsvd(frpca_t h, int64_t rows, int l, const float* X, int ldx, float*
     FRPCA_CHECK(rows >= l && l >= 1 && l <= kMaxL && ldx >= l && ldq >= l && X && Q && S, FRPCA_EINVAL,
                 "bad eigSVD arguments (need rows >= l)");
     if (tol <= 0.0) tol = kInnerTol;
-    DeviceTemp part(gram_partial_bytes(l)), rot(eig_log_bytes(l)), misc(6 * kMaxL * kMaxL * sizeof(double));
+    DeviceTemp part(gram_partial_bytes(l)), misc(6 * kMaxL * kMaxL * sizeof(double));
     double* G = static_cast<double*>(misc.p);
     double* W = G + kMaxL * kMaxL;
     double* B = W + kMaxL * kMaxL;
     double* d = B + kMaxL * kMaxL;
     double* diag = d + kMaxL;
     int* nsteps = reinterpret_cast<int*>(diag + kMaxL);
-    int* order = nsteps + 64;
     hipStream_t st = h->stream;
     launch_gram(X, false, ldx, nullptr, 0, rows, l, static_cast<double*>(part.p), G, l, st);
-    launch_eig(G, l, l, d, W, static_cast<double*>(rot.p), nsteps, order, diag, st);
+    launch_eig(G, l, l, d, W, nsteps, st);
     launch_eigsvd_coeffs(d, W, l, l, tol, B, S, st);
     launch_tsmm(X, false, ldx, rows, l, B, l, l, l, Q, ldq, nullptr, 0, false, st);
     check_launch();

@@ -2,21 +2,26 @@
 // epilogues of eigSVD (steps 3-5) and of the final steps of Alg. 5/6.
 //
 // Eigensolver: cyclic two-sided Jacobi with the parallel round-robin ordering (each round
-// pairs every index once; l-1 rounds make a sweep), in FP64, one workgroup. The upper
-// triangle of G lives in LDS; a round first computes the l/2 rotations (Golub & Van Loan,
-// sym.schur2: tau = (a_qq - a_pp)/(2 a_pq), t = sign(tau)/(|tau| + sqrt(1+tau^2))), then
-// every 2x2 block between two pairs is rotated from both sides by one thread. A rotation is
-// skipped when |a_pq| <= 1e-14 sqrt(a_pp a_qq) (relative test, so small eigenvalues keep
-// full relative accuracy); sweeps stop when a whole sweep skips everything. Rotations are
-// logged, and a second kernel rebuilds each row of the eigenvector matrix by replaying the
-// log, so G and W never need to share the LDS. Eigenvalues come out ascending (the order
-// Alg. 2 and ind = k+s:-1:s+1 rely on), ties in index order.
+// pairs every index once; N-1 rounds make a sweep), in FP64, one workgroup of 16 waves. The
+// upper triangle of G lives in LDS. A round first computes the N/2 rotations (Golub & Van
+// Loan, sym.schur2: tau = (a_qq - a_pp)/(2 a_pq), t = sign(tau)/(|tau| + sqrt(1+tau^2))),
+// then every 2x2 block between two pairs is rotated from both sides by one thread, while the
+// eigenvector matrix V (V <- V J) is updated in registers: wave w holds rows 8w..8w+7, lane
+// i holds the two columns of pair slot i. From one round to the next every index of slot
+// i >= 1 advances by one (mod N-1) and slot 0 keeps N-1, so the columns move between
+// neighbouring lanes (DPP wave shifts): a-columns shift down one lane (the last slot takes its
+// own b-column), b-columns shift up one lane (slot 1 takes slot 0's b, slot 0 takes slot 1's
+// a). A rotation is skipped when |a_pq| <= 1e-14 sqrt(a_pp a_qq) (relative test, so small
+// eigenvalues keep full relative accuracy); sweeps stop when a whole sweep skips everything.
+// Eigenvalues come out ascending (the order Alg. 2 and ind = k+s:-1:s+1 rely on), ties in
+// index order.
 #include "kernels.h"
 
 namespace frpca {
 namespace {
 
 constexpr int kEigThreads = 1024;
+constexpr int kVRows = 8;  // rows of V per wave (16 waves x 8 = 128)
 constexpr int kMaxSweeps = 40;
 constexpr double kJacobiTol = 1e-14;
 constexpr int kMaxN = kMaxL;  // even-padded size
@@ -27,65 +32,88 @@ __device__ __forceinline__ int packed(int i, int j, int n) {
 }
 __device__ __forceinline__ int pidx(int a, int b, int n) { return a <= b ? packed(a, b, n) : packed(b, a, n); }
 
-// Round-robin pair `slot` of round s for N (even) indices.
-__device__ __forceinline__ void rr_pair(int s, int slot, int N, int& p, int& q) {
-  int a, b;
-  if (slot == 0) {
-    a = N - 1;
-    b = s;
-  } else {
-    a = (s + slot) % (N - 1);
-    b = (s - slot + (N - 1)) % (N - 1);
-  }
-  p = min(a, b);
-  q = max(a, b);
+// lane i <- lane i+1 (0x130) and lane i <- lane i-1 (0x138), per 32-bit half
+__device__ __forceinline__ double from_next_lane(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), 0x130, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), 0x130, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double from_prev_lane(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), 0x138, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), 0x138, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
 }
 
-__global__ __launch_bounds__(kEigThreads) void jacobi_kernel(const double* G, int ldg, int l, double* rotlog,
-                                                             int* nsteps, double* diag_out) {
+// Indices of round-robin slot x at round 0; each round every index of a slot x >= 1 and the
+// second index of slot 0 advance by one modulo N-1.
+__device__ __forceinline__ void slot_start(int x, int N, int& a, int& b) {
+  if (x == 0) {
+    a = N - 1;
+    b = 0;
+  } else {
+    a = x;
+    b = N - 1 - x;
+  }
+}
+__device__ __forceinline__ int adv(int v, int N) { return (v + 1 == N - 1) ? 0 : v + 1; }
+__device__ __forceinline__ void slot_advance(int x, int N, int& a, int& b) {
+  if (x != 0) a = adv(a, N);
+  b = adv(b, N);
+}
+
+__global__ __launch_bounds__(kEigThreads) void jacobi_kernel(const double* G, int ldg, int l, double* d_out,
+                                                             double* W, int* nsweeps) {
   __shared__ double A[kMaxN * (kMaxN + 1) / 2];
-  __shared__ double rc[kMaxN / 2], rs[kMaxN / 2];
-  __shared__ int rflag[kMaxN / 2];
-  __shared__ unsigned short pairs[(kMaxN - 1) * (kMaxN / 2)];  // p | q << 8 for (round, slot)
-  __shared__ int rowbase[kMaxN];                               // packed(a, b) = rowbase[a] + b, a <= b
-  __shared__ unsigned char blk_i[kMaxN / 2 * (kMaxN / 2 - 1) / 2], blk_j[kMaxN / 2 * (kMaxN / 2 - 1) / 2];
+  __shared__ double2 rot[kMaxN / 2];
+  __shared__ double diag[kMaxN];
+  __shared__ int rank_s[kMaxN];
   __shared__ int any_rot;
   const int N = l + (l & 1);  // an odd size gets a zero dummy index that never rotates
   const int half = N / 2;
-  const int tid = threadIdx.x;
-  for (int a = tid; a < N; a += kEigThreads) rowbase[a] = a * N - (a * (a - 1)) / 2 - a;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int i = 0; i < N; ++i)
     for (int j = i + tid; j < N; j += kEigThreads)
       A[packed(i, j, N)] = (i < l && j < l) ? G[(size_t)i * ldg + j] : 0.0;
-  for (int e = tid; e < (N - 1) * half; e += kEigThreads) {
-    int p, q;
-    rr_pair(e / half, e % half, N, p, q);
-    pairs[e] = (unsigned short)(p | (q << 8));
-  }
+  // my (at most two) off-diagonal blocks (i < j) of pair slots and their current indices
   const int nblk = half * (half - 1) / 2;
-  for (int b = tid; b < nblk; b += kEigThreads) {
-    int i = 0, r = b;
+  int bi[2], bj[2], ai[2], bbi[2], aj[2], bbj[2];
+  bool has[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int b = tid + u * kEigThreads;
+    has[u] = b < nblk;
+    int i = 0, r = has[u] ? b : 0;
     while (r >= half - 1 - i) {
       r -= half - 1 - i;
       ++i;
     }
-    blk_i[b] = (unsigned char)i;
-    blk_j[b] = (unsigned char)(i + 1 + r);
+    bi[u] = i;
+    bj[u] = i + 1 + r;
+    slot_start(bi[u], N, ai[u], bbi[u]);
+    slot_start(bj[u], N, aj[u], bbj[u]);
+  }
+  // my pair slot (= lane) for the rotation (wave 0) and for V (all waves)
+  int sa, sb;
+  slot_start(lane, N, sa, sb);
+  const bool live = lane < half;
+  double va[kVRows], vb[kVRows];
+#pragma unroll
+  for (int k = 0; k < kVRows; ++k) {
+    const int r = kVRows * wave + k;
+    va[k] = (live && sa == r && r < l) ? 1.0 : 0.0;
+    vb[k] = (live && sb == r && r < l) ? 1.0 : 0.0;
   }
   __syncthreads();
-  auto pk = [&](int a, int b) { return a <= b ? rowbase[a] + b : rowbase[b] + a; };
-  int step = 0;
-  for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
+  int sweep = 0;
+  for (; sweep < kMaxSweeps; ++sweep) {
     if (tid == 0) any_rot = 0;
     __syncthreads();
-    for (int s = 0; s < N - 1; ++s, ++step) {
-      const unsigned short* pr = pairs + s * half;
+    for (int s = 0; s < N - 1; ++s) {
       if (tid < half) {
-        const int p = pr[tid] & 255, q = pr[tid] >> 8;
-        const int ipp = rowbase[p] + p, iqq = rowbase[q] + q, ipq = rowbase[p] + q;
+        const int p = min(sa, sb), q = max(sa, sb);
+        const int ipp = packed(p, p, N), iqq = packed(q, q, N), ipq = packed(p, q, N);
         const double app = A[ipp], aqq = A[iqq], apq = A[ipq];
         double c = 1.0, sn = 0.0;
-        int f = 0;
         if (apq != 0.0 && fabs(apq) > kJacobiTol * sqrt(fabs(app * aqq))) {
           const double tau = (aqq - app) / (2.0 * apq);
           const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
@@ -94,126 +122,88 @@ __global__ __launch_bounds__(kEigThreads) void jacobi_kernel(const double* G, in
           A[ipp] = app - t * apq;
           A[iqq] = aqq + t * apq;
           A[ipq] = 0.0;
-          f = 1;
           any_rot = 1;
         }
-        rc[tid] = c;
-        rs[tid] = sn;
-        rflag[tid] = f;
-        rotlog[((size_t)step * (kMaxN / 2) + tid) * 2 + 0] = c;
-        rotlog[((size_t)step * (kMaxN / 2) + tid) * 2 + 1] = sn;
+        rot[tid] = make_double2(c, sn);
       }
       __syncthreads();
-      for (int b = tid; b < nblk; b += kEigThreads) {
-        const int i = blk_i[b], j = blk_j[b];
-        if (!(rflag[i] | rflag[j])) continue;
-        const int p = pr[i] & 255, q = pr[i] >> 8, r = pr[j] & 255, t = pr[j] >> 8;
-        const double ci = rc[i], si = rs[i], cj = rc[j], sj = rs[j];
-        const int ipr = pk(p, r), ipt = pk(p, t), iqr = pk(q, r), iqt = pk(q, t);
-        const double gpr = A[ipr], gpt = A[ipt], gqr = A[iqr], gqt = A[iqt];
-        // rows: (J_i^T G)
-        const double xr = ci * gpr - si * gqr, yr = si * gpr + ci * gqr;
-        const double xt = ci * gpt - si * gqt, yt = si * gpt + ci * gqt;
-        // columns: (. J_j)
-        A[ipr] = cj * xr - sj * xt;
-        A[ipt] = sj * xr + cj * xt;
-        A[iqr] = cj * yr - sj * yt;
-        A[iqt] = sj * yr + cj * yt;
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        if (has[u]) {
+          const double2 ri = rot[bi[u]], rj = rot[bj[u]];
+          if (ri.y != 0.0 || rj.y != 0.0) {
+            const int p = min(ai[u], bbi[u]), q = max(ai[u], bbi[u]);
+            const int r = min(aj[u], bbj[u]), t = max(aj[u], bbj[u]);
+            const int ipr = pidx(p, r, N), ipt = pidx(p, t, N), iqr = pidx(q, r, N), iqt = pidx(q, t, N);
+            const double gpr = A[ipr], gpt = A[ipt], gqr = A[iqr], gqt = A[iqt];
+            // rows: (J_i^T G)
+            const double xr = ri.x * gpr - ri.y * gqr, yr = ri.y * gpr + ri.x * gqr;
+            const double xt = ri.x * gpt - ri.y * gqt, yt = ri.y * gpt + ri.x * gqt;
+            // columns: (. J_j)
+            A[ipr] = rj.x * xr - rj.y * xt;
+            A[ipt] = rj.y * xr + rj.x * xt;
+            A[iqr] = rj.x * yr - rj.y * yt;
+            A[iqt] = rj.y * yr + rj.x * yt;
+          }
+        }
+      }
+      // V <- V J on this wave's rows, then move the columns to next round's slots
+      {
+        const double2 rr = live ? rot[lane] : make_double2(1.0, 0.0);
+        const bool aq = sa < sb;
+#pragma unroll
+        for (int k = 0; k < kVRows; ++k) {
+          if (rr.y != 0.0) {
+            const double vp = aq ? va[k] : vb[k], vq = aq ? vb[k] : va[k];
+            const double np = rr.x * vp - rr.y * vq, nq = rr.y * vp + rr.x * vq;
+            va[k] = aq ? np : nq;
+            vb[k] = aq ? nq : np;
+          }
+          if (half > 1) {
+            const double t1 = from_next_lane(va[k]);
+            const double t2 = from_prev_lane(vb[k]);
+            const double na = (lane == 0) ? va[k] : (lane == half - 1 ? vb[k] : t1);
+            const double nb = (lane == 0) ? t1 : t2;
+            va[k] = na;
+            vb[k] = nb;
+          }
+        }
+      }
+      slot_advance(lane, N, sa, sb);
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        slot_advance(bi[u], N, ai[u], bbi[u]);
+        slot_advance(bj[u], N, aj[u], bbj[u]);
       }
       __syncthreads();
     }
     if (!any_rot) break;
     __syncthreads();
   }
-  if (tid == 0) *nsteps = step;
-  for (int i = tid; i < l; i += kEigThreads) diag_out[i] = A[rowbase[i] + i];
-}
-
-// Eigenvalues in ascending order (ties by index) and the rank of each original index.
-__global__ __launch_bounds__(128) void eig_sort_kernel(const double* diag, int l, double* d, int* rank) {
-  const int i = threadIdx.x;
-  if (i >= l) return;
-  const double v = diag[i];
-  int r = 0;
-  for (int j = 0; j < l; ++j) {
-    const double u = diag[j];
-    r += (u < v) || (u == v && j < i);
-  }
-  rank[i] = r;
-  d[r] = v;
-}
-
-// Row `blockIdx.x` of the eigenvector matrix: e_r^T J_1 J_2 ... J_T, replayed from the log
-// by one wave with the row in registers. Lane i holds the two entries of round-robin slot i
-// (indices ia, ib). From one round to the next every index of slot i >= 1 advances by one
-// (mod N-1) and slot 0 keeps N-1, which moves the values between neighbouring lanes:
-// a-values shift down one lane (the last slot takes its own b-value), b-values shift up one
-// lane (slot 1 takes slot 0's b, slot 0 takes slot 1's a).
-__global__ __launch_bounds__(64) void eigvec_kernel(const double* rotlog, const int* nsteps, int l, const int* rank,
-                                                    double* W) {
-  const int r = blockIdx.x;
-  const int lane = threadIdx.x;
-  const int N = l + (l & 1), half = N / 2;
-  const bool live = lane < half;
-  int ia, ib;
-  if (lane == 0) {
-    ia = N - 1;
-    ib = 0;
-  } else {
-    ia = lane;
-    ib = N - 1 - lane;
-  }
-  double va = (ia == r) ? 1.0 : 0.0, vb = (ib == r) ? 1.0 : 0.0;
-  const int T = *nsteps;
-  constexpr int kPre = 8;
-  double cb[kPre], sb[kPre], cn[kPre], sn[kPre];
-  auto fetch = [&](int st0, double* c, double* s) {
-#pragma unroll
-    for (int u = 0; u < kPre; ++u) {
-      c[u] = 1.0;
-      s[u] = 0.0;
-      if (live && st0 + u < T) {
-        c[u] = rotlog[((size_t)(st0 + u) * (kMaxN / 2) + lane) * 2 + 0];
-        s[u] = rotlog[((size_t)(st0 + u) * (kMaxN / 2) + lane) * 2 + 1];
-      }
+  if (tid == 0) *nsweeps = sweep + 1;
+  // eigenvalues in ascending order, ties by index
+  if (tid < l) diag[tid] = A[packed(tid, tid, N)];
+  __syncthreads();
+  if (tid < l) {
+    const double v = diag[tid];
+    int r = 0;
+    for (int j = 0; j < l; ++j) {
+      const double u = diag[j];
+      r += (u < v) || (u == v && j < tid);
     }
-  };
-  fetch(0, cb, sb);
-  const int up = min(lane + 1, 63), dn = max(lane - 1, 0);
-  for (int st0 = 0; st0 < T; st0 += kPre) {
-    fetch(st0 + kPre, cn, sn);  // next batch in flight while this one is applied
-#pragma unroll
-    for (int u = 0; u < kPre; ++u) {
-      if (st0 + u < T) {
-        if (sb[u] != 0.0) {
-          // the logged rotation is for (p, q) = (min, max) of the slot's indices
-          const bool aq = ia < ib;
-          const double vp = aq ? va : vb, vq = aq ? vb : va;
-          const double np = cb[u] * vp - sb[u] * vq, nq = sb[u] * vp + cb[u] * vq;
-          va = aq ? np : nq;
-          vb = aq ? nq : np;
-        }
-        if (half > 1) {  // with a single pair nothing moves
-          const double t1 = __shfl(va, up);
-          const double t2 = __shfl(vb, dn);
-          const double na = (lane == 0) ? va : (lane == half - 1 ? vb : t1);
-          const double nb = (lane == 0) ? t1 : t2;
-          va = na;
-          vb = nb;
-        }
-        if (lane != 0) ia = (ia + 1 == N - 1) ? 0 : ia + 1;
-        ib = (ib + 1 == N - 1) ? 0 : ib + 1;
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < kPre; ++u) {
-      cb[u] = cn[u];
-      sb[u] = sn[u];
-    }
+    rank_s[tid] = r;
+    d_out[r] = v;
   }
+  __syncthreads();
   if (live) {
-    if (ia < l) W[(size_t)r * l + rank[ia]] = va;
-    if (ib < l) W[(size_t)r * l + rank[ib]] = vb;
+#pragma unroll
+    for (int k = 0; k < kVRows; ++k) {
+      const int r = kVRows * wave + k;
+      if (r < l) {
+        if (sa < l) W[(size_t)r * l + rank_s[sa]] = va[k];
+        if (sb < l) W[(size_t)r * l + rank_s[sb]] = vb[k];
+      }
+    }
   }
 }
 
@@ -291,23 +281,41 @@ __global__ __launch_bounds__(256) void sign_partial_kernel(const float* V, int64
   }
 }
 
-__global__ __launch_bounds__(128) void sign_final_kernel(const float* V, int k, int nblk, const float* pv,
+// One block per column i: reduce the per-block candidates (|v|, row) in block order (ties:
+// lowest row), then fold the sign into column i of Blong.
+__global__ __launch_bounds__(256) void sign_final_kernel(const float* V, int k, int nblk, const float* pv,
                                                          const int* pr, float* sgn, double* Blong, int ldb, int l) {
-  const int i = threadIdx.x;
-  if (i >= k) return;
+  __shared__ float sv[256];
+  __shared__ int sr[256];
+  const int i = blockIdx.x, t = threadIdx.x;
   float best = -1.0f;
   int brow = 0;
-  for (int b = 0; b < nblk; ++b) {
+  for (int b = t; b < nblk; b += 256) {
     const float a = pv[(size_t)b * k + i];
-    if (a > best) {
+    const int r = pr[(size_t)b * k + i];
+    if (a > best || (a == best && r < brow)) {
       best = a;
-      brow = pr[(size_t)b * k + i];
+      brow = r;
     }
   }
-  const float s = (V[(size_t)brow * k + i] < 0.0f) ? -1.0f : 1.0f;
-  sgn[i] = s;
+  sv[t] = best;
+  sr[t] = brow;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (t < off) {
+      const float a = sv[t + off];
+      const int r = sr[t + off];
+      if (a > sv[t] || (a == sv[t] && r < sr[t])) {
+        sv[t] = a;
+        sr[t] = r;
+      }
+    }
+    __syncthreads();
+  }
+  const float s = (V[(size_t)sr[0] * k + i] < 0.0f) ? -1.0f : 1.0f;
+  if (t == 0) sgn[i] = s;
   if (s < 0.0f)
-    for (int a = 0; a < l; ++a) Blong[(size_t)a * ldb + i] = -Blong[(size_t)a * ldb + i];
+    for (int a = t; a < l; a += 256) Blong[(size_t)a * ldb + i] = -Blong[(size_t)a * ldb + i];
 }
 
 __global__ __launch_bounds__(256) void sign_apply_kernel(float* V, int64_t rows, int k, const float* sgn) {
@@ -319,13 +327,8 @@ __global__ __launch_bounds__(256) void sign_apply_kernel(float* V, int64_t rows,
 
 }  // namespace
 
-size_t eig_log_bytes(int /*l*/) { return (size_t)kMaxSweeps * (kMaxN - 1) * (kMaxN / 2) * 2 * sizeof(double); }
-
-void launch_eig(const double* G, int ldg, int l, double* d, double* W, double* rotlog, int* nsteps, int* order,
-                double* diag_tmp, hipStream_t st) {
-  jacobi_kernel<<<1, kEigThreads, 0, st>>>(G, ldg, l, rotlog, nsteps, diag_tmp);
-  eig_sort_kernel<<<1, 128, 0, st>>>(diag_tmp, l, d, order);
-  eigvec_kernel<<<l, 64, 0, st>>>(rotlog, nsteps, l, order, W);
+void launch_eig(const double* G, int ldg, int l, double* d, double* W, int* nsweeps, hipStream_t st) {
+  jacobi_kernel<<<1, kEigThreads, 0, st>>>(G, ldg, l, d, W, nsweeps);
 }
 
 void launch_eigsvd_coeffs(const double* d, const double* W, int l, int ldb, double tol, double* B, double* sigma,
@@ -351,7 +354,7 @@ void launch_sign_fix(float* V, int64_t rows, int k, double* Blong, int ldb, int 
   int* pr = reinterpret_cast<int*>(pv + nblk * k);
   float* sgn = reinterpret_cast<float*>(pr + nblk * k);
   sign_partial_kernel<<<(unsigned)nblk, 256, 0, st>>>(V, rows, k, pv, pr);
-  sign_final_kernel<<<1, 128, 0, st>>>(V, k, (int)nblk, pv, pr, sgn, Blong, ldb, brows);
+  sign_final_kernel<<<k, 256, 0, st>>>(V, k, (int)nblk, pv, pr, sgn, Blong, ldb, brows);
   sign_apply_kernel<<<(unsigned)((rows * k + 255) / 256), 256, 0, st>>>(V, rows, k, sgn);
 }
 

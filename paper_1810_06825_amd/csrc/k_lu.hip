@@ -48,7 +48,7 @@ struct SelectArgs {
 
 template <int LP>
 __global__ __launch_bounds__(kNode) void lu_select_kernel(SelectArgs a) {
-  __shared__ float piv[2][LP];
+  __shared__ __align__(16) float piv[2][LP];
   __shared__ float red_v[kWaves];
   __shared__ int red_w[kWaves];
   __shared__ int cand[kNode];
@@ -178,9 +178,10 @@ __global__ __launch_bounds__(kNode) void lu_select_kernel(SelectArgs a) {
         }
         if (bv > thr) {
           float* pr = piv[j & 1];
+          float4* pr4 = reinterpret_cast<float4*>(pr);
           if (t == bw) {
 #pragma unroll
-            for (int c = 0; c < LP; ++c) pr[c] = row[c];
+            for (int c = 0; c < LP; c += 4) pr4[c / 4] = make_float4(row[c], row[c + 1], row[c + 2], row[c + 3]);
             act = false;
             a.sel_out[node * kMaxL + cnt] = myrow;
             a.col_out[node * kMaxL + cnt] = j;
@@ -191,8 +192,16 @@ __global__ __launch_bounds__(kNode) void lu_select_kernel(SelectArgs a) {
 #pragma unroll
             for (int cb = 0; cb < NC; ++cb) {
               if (cb < NC - jb) {
-#pragma unroll
-                for (int c = 8 * cb; c < 8 * cb + 8; ++c) row[c] = fmaf(-f, pr[c], row[c]);
+                const float4 p0 = pr4[2 * cb], p1 = pr4[2 * cb + 1];  // broadcast 16-byte reads
+                const int c = 8 * cb;
+                row[c + 0] = fmaf(-f, p0.x, row[c + 0]);
+                row[c + 1] = fmaf(-f, p0.y, row[c + 1]);
+                row[c + 2] = fmaf(-f, p0.z, row[c + 2]);
+                row[c + 3] = fmaf(-f, p0.w, row[c + 3]);
+                row[c + 4] = fmaf(-f, p1.x, row[c + 4]);
+                row[c + 5] = fmaf(-f, p1.y, row[c + 5]);
+                row[c + 6] = fmaf(-f, p1.z, row[c + 6]);
+                row[c + 7] = fmaf(-f, p1.w, row[c + 7]);
               }
             }
           }
@@ -209,11 +218,13 @@ __global__ __launch_bounds__(kNode) void lu_select_kernel(SelectArgs a) {
 }
 
 // Factor the root's pivot rows without further pivoting in FP64, invert U in place and
-// scatter U^-1 into B (l x ldb). Thread u owns row u of the r x r pivot block.
+// scatter U^-1 into B (l x ldb). Thread u owns row u of the r x r pivot block; the LDS row
+// stride is odd (kMS doubles) so a column access by all threads hits distinct banks.
+constexpr int kMS = kMaxL + 1;
 __global__ __launch_bounds__(256) void lu_factor_kernel(const float* X, int ldx, int l, const int32_t* sel,
                                                         const int32_t* selcol, const int32_t* cnt_p, double* B,
                                                         int ldb, int* ndropped) {
-  __shared__ double M[kMaxL * kMaxL];
+  __shared__ double M[kMaxL * kMS];
   __shared__ int colpos[kMaxL];
   __shared__ int colid[kMaxL];
   const int t = threadIdx.x;
@@ -227,14 +238,14 @@ __global__ __launch_bounds__(256) void lu_factor_kernel(const float* X, int ldx,
   __syncthreads();
   if (t < r) {
     const float* src = X + (size_t)sel[t] * ldx;
-    for (int j = 0; j < r; ++j) M[t * kMaxL + j] = (double)src[colid[j]];
+    for (int j = 0; j < r; ++j) M[t * kMS + j] = (double)src[colid[j]];
   }
   __syncthreads();
   // Doolittle elimination: after step s, row s holds row s of U
   for (int s = 0; s < r; ++s) {
     if (t > s && t < r) {
-      const double f = M[t * kMaxL + s] / M[s * kMaxL + s];
-      for (int v = s + 1; v < r; ++v) M[t * kMaxL + v] -= f * M[s * kMaxL + v];
+      const double f = M[t * kMS + s] / M[s * kMS + s];
+      for (int v = s + 1; v < r; ++v) M[t * kMS + v] -= f * M[s * kMS + v];
     }
     __syncthreads();
   }
@@ -243,17 +254,17 @@ __global__ __launch_bounds__(256) void lu_factor_kernel(const float* X, int ldx,
     double val = 0.0;
     const int j = t;
     if (j >= i && j < r) {
-      const double dinv = 1.0 / M[i * kMaxL + i];
+      const double dinv = 1.0 / M[i * kMS + i];
       if (j == i) {
         val = dinv;
       } else {
         double acc = 0.0;
-        for (int k = i + 1; k <= j; ++k) acc += M[i * kMaxL + k] * M[k * kMaxL + j];
+        for (int k = i + 1; k <= j; ++k) acc += M[i * kMS + k] * M[k * kMS + j];
         val = -dinv * acc;
       }
     }
     __syncthreads();
-    if (j >= i && j < r) M[i * kMaxL + j] = val;
+    if (j >= i && j < r) M[i * kMS + j] = val;
     __syncthreads();
   }
   for (int a = 0; a < l; ++a) {
@@ -261,7 +272,7 @@ __global__ __launch_bounds__(256) void lu_factor_kernel(const float* X, int ldx,
       double v = 0.0;
       if (b < l) {
         const int pa = colpos[a], pb = colpos[b];
-        if (pa >= 0 && pb >= 0 && pa <= pb) v = M[pa * kMaxL + pb];
+        if (pa >= 0 && pb >= 0 && pa <= pb) v = M[pa * kMS + pb];
       }
       B[(size_t)a * ldb + b] = v;
     }
