@@ -70,7 +70,6 @@ typedef struct {
   int rank_dropped;       /* output singular values set to 0 by rank_tol (last run)   */
   size_t workspace_bytes; /* device memory currently held by the handle               */
   double create_ms;       /* wall time of frpca_create (validation + CSC mirror)       */
-  int eig_sweeps;         /* Jacobi sweeps of the last eigendecomposition of a run      */
   double t_ms[FRPCA_NTIMERS];   /* accumulated GPU time per kernel class (opts.timing) */
   int64_t t_count[FRPCA_NTIMERS]; /* number of timed launches per class                */
 } frpca_info;

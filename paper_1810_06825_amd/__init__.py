@@ -91,7 +91,7 @@ class FrPCA:
         return {
             "m": inf.m, "n": inf.n, "nnz": inf.nnz, "orientation": inf.orientation, "k": inf.k,
             "s": inf.s, "passes": inf.passes, "rank_dropped": inf.rank_dropped,
-            "workspace_bytes": inf.workspace_bytes, "create_ms": inf.create_ms, "eig_sweeps": inf.eig_sweeps,
+            "workspace_bytes": inf.workspace_bytes, "create_ms": inf.create_ms,
             "t_ms": {n: inf.t_ms[i] for i, n in enumerate(TIMER_NAMES)},
             "t_count": {n: inf.t_count[i] for i, n in enumerate(TIMER_NAMES)},
         }

@@ -36,7 +36,7 @@ class FrpcaOpts(ctypes.Structure):
 class FrpcaInfo(ctypes.Structure):
     _fields_ = [("m", c_int64), ("n", c_int64), ("nnz", c_int64), ("orientation", c_int),
                 ("k", c_int), ("s", c_int), ("passes", c_int), ("rank_dropped", c_int),
-                ("workspace_bytes", c_size_t), ("create_ms", c_double), ("eig_sweeps", c_int),
+                ("workspace_bytes", c_size_t), ("create_ms", c_double),
                 ("t_ms", c_double * NTIMERS), ("t_count", c_int64 * NTIMERS)]
 
 

@@ -94,9 +94,10 @@ struct frpca_ctx {
   int ws_bf16 = -1;
   float *Q = nullptr, *X = nullptr, *Y = nullptr, *Z = nullptr;
   uint16_t *Qb = nullptr, *Yb = nullptr;
-  double *gram_part = nullptr, *G = nullptr, *W = nullptr, *d = nullptr, *diag = nullptr;
+  double *gram_part = nullptr, *G = nullptr, *W = nullptr, *d = nullptr;
   double *B1 = nullptr, *B2 = nullptr;
-  int *order = nullptr, *nsteps = nullptr, *ndrop = nullptr;
+  int *order = nullptr, *ndrop = nullptr;
+  double* eig_tmp = nullptr;
   void *lu_tmp = nullptr, *sign_tmp = nullptr;
 
   // backward workspace
@@ -226,9 +227,8 @@ struct frpca_ctx {
       B1 = a.take<double>(kMaxL * kMaxL);
       B2 = a.take<double>(kMaxL * kMaxL);
       d = a.take<double>(kMaxL);
-      diag = a.take<double>(kMaxL);
       order = a.take<int>(kMaxL);
-      nsteps = a.take<int>(4);
+      eig_tmp = a.take<double>(eig_scratch_bytes() / sizeof(double));
       ndrop = a.take<int>(4);
       lu_tmp = a.take<char>(lu_temp_bytes(Ns, lp));
       sign_tmp = a.take<char>(sign_partial_bytes(Nl, kMaxL));
@@ -438,7 +438,7 @@ int frpca_run(frpca_t h, int k, int p_passes, int s_oversample, uint64_t seed, f
         launch_gram(P, false, LP, nullptr, 0, rows, l, h->gram_part, h->G, l, st);
       }
       frpca_ctx::Scope t(h, FRPCA_T_EIG);
-      launch_eig(h->G, l, l, h->d, h->W, h->nsteps, st);
+      launch_eig(h->G, l, l, h->d, h->W, h->eig_tmp, st);
     };
     auto orth_eig = [&] {
       gram_eig(h->X, Ns);
@@ -569,12 +569,10 @@ int frpca_get_info(frpca_t h, frpca_info* info) {
     FRPCA_CHECK(info != nullptr, FRPCA_EINVAL, "NULL info");
     h->collect_timers();
     if (h->ws) {
-      int nd = 0, sw = 0;
+      int nd = 0;
       FRPCA_HIP(hipMemcpyAsync(&nd, h->ndrop, sizeof(int), hipMemcpyDeviceToHost, h->stream));
-      FRPCA_HIP(hipMemcpyAsync(&sw, h->nsteps, sizeof(int), hipMemcpyDeviceToHost, h->stream));
       FRPCA_HIP(hipStreamSynchronize(h->stream));
       h->info.rank_dropped = nd;
-      h->info.eig_sweeps = sw;
     }
     h->info.workspace_bytes = h->setup_bytes + h->ws_bytes + h->bws_bytes;
     *info = h->info;
@@ -642,8 +640,8 @@ int frpca_eig(frpca_t h, int l, const double* G, double* W, double* d) {
   if (!h) return fail(nullptr, Error{FRPCA_EINVAL, "NULL handle"});
   return guarded(h, [&] {
     FRPCA_CHECK(l >= 1 && l <= kMaxL && G && W && d, FRPCA_EINVAL, "bad eig arguments");
-    DeviceTemp misc(256);
-    launch_eig(G, l, l, d, W, static_cast<int*>(misc.p), h->stream);
+    DeviceTemp misc(eig_scratch_bytes());
+    launch_eig(G, l, l, d, W, static_cast<double*>(misc.p), h->stream);
     check_launch();
     FRPCA_HIP(hipStreamSynchronize(h->stream));
   });
@@ -656,16 +654,14 @@ int frpca_eigsvd(frpca_t h, int64_t rows, int l, const float* X, int ldx, float*
     FRPCA_CHECK(rows >= l && l >= 1 && l <= kMaxL && ldx >= l && ldq >= l && X && Q && S, FRPCA_EINVAL,
                 "bad eigSVD arguments (need rows >= l)");
     if (tol <= 0.0) tol = kInnerTol;
-    DeviceTemp part(gram_partial_bytes(l)), misc(6 * kMaxL * kMaxL * sizeof(double));
+    DeviceTemp part(gram_partial_bytes(l)), misc(4 * kMaxL * kMaxL * sizeof(double)), etmp(eig_scratch_bytes());
     double* G = static_cast<double*>(misc.p);
     double* W = G + kMaxL * kMaxL;
     double* B = W + kMaxL * kMaxL;
     double* d = B + kMaxL * kMaxL;
-    double* diag = d + kMaxL;
-    int* nsteps = reinterpret_cast<int*>(diag + kMaxL);
     hipStream_t st = h->stream;
     launch_gram(X, false, ldx, nullptr, 0, rows, l, static_cast<double*>(part.p), G, l, st);
-    launch_eig(G, l, l, d, W, nsteps, st);
+    launch_eig(G, l, l, d, W, static_cast<double*>(etmp.p), st);
     launch_eigsvd_coeffs(d, W, l, l, tol, B, S, st);
     launch_tsmm(X, false, ldx, rows, l, B, l, l, l, Q, ldq, nullptr, 0, false, st);
     check_launch();

@@ -75,9 +75,11 @@ void launch_tsmm(const void* X, bool x_bf16, int ldx, int64_t rows, int kdim, co
                  int ldb, int c, int c_out, float* out, int ldo, uint16_t* out_bf16, int ldo16,
                  bool accumulate, hipStream_t st);
 
-// Symmetric eigendecomposition by cyclic Jacobi (G: l x l FP64, ldg). d ascending, W l x l
-// (column j pairs with d[j]); *nsweeps receives the number of sweeps used.
-void launch_eig(const double* G, int ldg, int l, double* d, double* W, int* nsweeps, hipStream_t st);
+// Symmetric eigendecomposition (G: l x l FP64, ldg): Householder tridiagonalization, then
+// relatively robust representations. d ascending, W l x l row-major (column j pairs with
+// d[j]); scratch holds eig_scratch_bytes() of device memory.
+size_t eig_scratch_bytes();
+void launch_eig(const double* G, int ldg, int l, double* d, double* W, double* scratch, hipStream_t st);
 // eigSVD basis coefficients: B[a][j] = W[a][j] / sigma_j (0 if sigma_j <= tol*max), sigma out.
 void launch_eigsvd_coeffs(const double* d, const double* W, int l, int ldb, double tol,
                           double* B, double* sigma, hipStream_t st);

@@ -143,18 +143,33 @@ def test_gram_fp64_accumulation(l):
 
 
 @pytest.mark.parametrize("l,kind", [(15, "spread"), (60, "spread"), (120, "spread"), (128, "cluster"),
-                                    (7, "degenerate"), (2, "spread")])
-def test_jacobi_eig(l, kind):
+                                    (7, "degenerate"), (2, "spread"), (1, "spread"), (3, "spread"),
+                                    (128, "indefinite"), (100, "multiplicity"), (100, "psd_wide"),
+                                    (64, "identity"), (20, "diagonal"), (120, "gram_rank40")])
+def test_eig(l, kind):
+    """Eigendecomposition of symmetric matrices with wide, clustered, repeated, indefinite and
+    rank-deficient spectra: eigenvalues, residual and orthogonality at FP64 level."""
     rng = np.random.default_rng(l)
     Qr = np.linalg.qr(rng.standard_normal((l, l)))[0]
-    if kind == "spread":
-        d = np.geomspace(1e-8, 1e4, l)
-    elif kind == "cluster":
-        d = 1.0 + 1e-9 * rng.standard_normal(l)
-        d[:5] = [1e3, 1e2, 10, 1e-3, 1e-6]
-    else:
-        d = np.array([0.0, 0.0, 1.0, 1.0, 1.0, 5.0, 9.0])
-    G = (Qr * d) @ Qr.T
+    spectra = {
+        "spread": lambda: np.geomspace(1e-8, 1e4, l),
+        "cluster": lambda: np.concatenate([[1e3, 1e2, 10, 1e-3, 1e-6], 1.0 + 1e-9 * rng.standard_normal(l - 5)]),
+        "degenerate": lambda: np.array([0.0, 0.0, 1.0, 1.0, 1.0, 5.0, 9.0]),
+        "multiplicity": lambda: np.repeat([1.0, 2.0, 3.0, 4.0], l // 4),
+        "psd_wide": lambda: np.concatenate([np.geomspace(1, 1e-14, l // 2), np.zeros(l - l // 2)]),
+    }
+    if kind in spectra:
+        G = (Qr * spectra[kind]()) @ Qr.T
+    elif kind == "indefinite":
+        B = rng.standard_normal((l, l))
+        G = B + B.T
+    elif kind == "identity":
+        G = np.eye(l)
+    elif kind == "diagonal":
+        G = np.diag(rng.permutation(np.arange(1.0, l + 1)))
+    else:  # gram_rank40
+        X = rng.standard_normal((500, 40)) @ rng.standard_normal((40, l))
+        G = X.T @ X
     G = (G + G.T) / 2
     say("eig", l, kind)
     mat = _mat(random_sparse(8, 8, 0.5, seed=1))
