@@ -162,9 +162,11 @@ int frpca_spmm(frpca_t h, int trans, int l, const void* in, int in_bf16, int ld_
  * (l columns), G: device double[l*l] row-major, accumulated in FP64 on MFMA. */
 int frpca_gram(frpca_t h, int64_t rows, int l, const float* X, int ldx, double* G);
 
-/* Symmetric eigendecomposition (Alg. 2 step 2) by cyclic parallel Jacobi in FP64:
+/* Symmetric eigendecomposition (Alg. 2 step 2) in FP64 (Householder tridiagonalization,
+ * then bisection and twisted factorizations on a positive definite L D L^T representation):
  * G (device double[l*l], symmetric) = W diag(d) W^T with d ascending (device double[l])
- * and orthonormal W (device double[l*l], column j pairs with d[j]). l <= 128. */
+ * and orthonormal W (device double[l*l] row-major, column j pairs with d[j]). l <= 128.
+ * Allocates and frees a 256 KiB device scratch buffer per call. */
 int frpca_eig(frpca_t h, int l, const double* G, double* W, double* d);
 
 /* eigSVD basis (Alg. 2): Q = X V diag(1/S) with S ascending; S_j <= tol * max(S) gives a
