@@ -20,6 +20,7 @@ namespace {
 constexpr int kNode = 512;   // rows per tournament node (one per thread)
 constexpr int kFanIn = 4;    // candidate sets merged per node (4 * 128 <= 512)
 constexpr int kWaves = kNode / 64;
+static_assert(kNode <= 512, "the argmax key keeps 9 bits for the row slot");
 
 template <int B, int E, class F>
 __device__ __forceinline__ void static_for(F&& f) {
@@ -27,6 +28,21 @@ __device__ __forceinline__ void static_for(F&& f) {
     f(std::integral_constant<int, B>{});
     static_for<B + 1, E>(f);
   }
+}
+
+// Largest 32-bit key of the wave: DPP row shifts 1, 2, 4, 8 (lane 15 of each row of 16 then
+// holds its row's maximum; lanes whose source falls outside the row keep their own key), then
+// the four row maxima through readlane. Every lane gets the result. All 64 lanes must be active.
+__device__ __forceinline__ uint32_t wave_max_key(uint32_t k) {
+  k = max(k, (uint32_t)__builtin_amdgcn_update_dpp((int)k, (int)k, 0x111, 0xF, 0xF, false));
+  k = max(k, (uint32_t)__builtin_amdgcn_update_dpp((int)k, (int)k, 0x112, 0xF, 0xF, false));
+  k = max(k, (uint32_t)__builtin_amdgcn_update_dpp((int)k, (int)k, 0x114, 0xF, 0xF, false));
+  k = max(k, (uint32_t)__builtin_amdgcn_update_dpp((int)k, (int)k, 0x118, 0xF, 0xF, false));
+  const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)k, 15);
+  const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)k, 31);
+  const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)k, 47);
+  const uint32_t d = (uint32_t)__builtin_amdgcn_readlane((int)k, 63);
+  return max(max(a, b), max(c, d));
 }
 
 struct SelectArgs {
@@ -50,7 +66,7 @@ template <int LP>
 __global__ __launch_bounds__(kNode) void lu_select_kernel(SelectArgs a) {
   __shared__ __align__(16) float piv[2][LP];
   __shared__ float red_v[kWaves];
-  __shared__ int red_w[kWaves];
+  __shared__ __align__(16) uint32_t red_k[2][kWaves];
   __shared__ int cand[kNode];
   __shared__ int ncand_s;
   __shared__ float thr_s;
@@ -149,33 +165,19 @@ __global__ __launch_bounds__(kNode) void lu_select_kernel(SelectArgs a) {
     for (int jr = 0; jr < 8; ++jr) {
       const int j = 8 * jb + jr;
       if (j < a.l) {
-        float v = act ? fabsf(row[jr]) : -1.0f;
-        int who = t;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-          const float ov = __shfl_xor(v, off);
-          const int ow = __shfl_xor(who, off);
-          if (ov > v || (ov == v && ow < who)) {
-            v = ov;
-            who = ow;
-          }
-        }
-        if (lane == 0) {
-          red_v[wave] = v;
-          red_w[wave] = who;
-        }
+        // argmax key: |value| with its 9 lowest mantissa bits replaced by (511 - thread), so
+        // the maximum picks the largest magnitude (to 2^-14 relative) and, among those, the
+        // lowest row slot; retired rows give 0
+        const uint32_t key =
+            act ? ((__float_as_uint(fabsf(row[jr])) & ~0x1FFu) | (uint32_t)(kNode - 1 - t)) : 0u;
+        const uint32_t wk = wave_max_key(key);
+        if (lane == 0) red_k[j & 1][wave] = wk;
         __syncthreads();
-        float bv = red_v[0];
-        int bw = red_w[0];
+        uint32_t best = red_k[j & 1][0];
 #pragma unroll
-        for (int w = 1; w < kWaves; ++w) {
-          const float ov = red_v[w];
-          const int ow = red_w[w];
-          if (ov > bv || (ov == bv && ow < bw)) {
-            bv = ov;
-            bw = ow;
-          }
-        }
+        for (int w = 1; w < kWaves; ++w) best = max(best, red_k[j & 1][w]);
+        const int bw = kNode - 1 - (int)(best & 0x1FFu);
+        const float bv = __uint_as_float(best & ~0x1FFu);
         if (bv > thr) {
           float* pr = piv[j & 1];
           float4* pr4 = reinterpret_cast<float4*>(pr);
@@ -188,7 +190,9 @@ __global__ __launch_bounds__(kNode) void lu_select_kernel(SelectArgs a) {
           }
           __syncthreads();
           if (act) {
-            const float f = row[jr] / pr[jr];
+            // the multiplier only steers which rows survive the tournament (the pivot rows are
+            // refactored in FP64 afterwards), so the hardware reciprocal is accurate enough
+            const float f = row[jr] * __builtin_amdgcn_rcpf(pr[jr]);
 #pragma unroll
             for (int cb = 0; cb < NC; ++cb) {
               if (cb < NC - jb) {
@@ -218,15 +222,21 @@ __global__ __launch_bounds__(kNode) void lu_select_kernel(SelectArgs a) {
 }
 
 // Factor the root's pivot rows without further pivoting in FP64, invert U in place and
-// scatter U^-1 into B (l x ldb). Thread u owns row u of the r x r pivot block; the LDS row
-// stride is odd (kMS doubles) so a column access by all threads hits distinct banks.
+// scatter U^-1 into B (l x ldb). One workgroup of 1024 threads on an r x r block in LDS with an
+// odd row stride (kMS doubles):
+//  * Doolittle: at step s the multipliers of column s are formed, then the trailing block is
+//    updated by 8 row phases x 128 columns (a wave covers 64 consecutive columns of one row).
+//  * U^-1 column by column (T[j][j] = 1/U[j][j], T[0:j, j] = -T[j][j] T[0:j, 0:j] U[0:j, j],
+//    the already inverted leading block in place): eight lanes per row share each dot product.
 constexpr int kMS = kMaxL + 1;
-__global__ __launch_bounds__(256) void lu_factor_kernel(const float* X, int ldx, int l, const int32_t* sel,
+constexpr int kFT = 1024;
+__global__ __launch_bounds__(kFT) void lu_factor_kernel(const float* X, int ldx, int l, const int32_t* sel,
                                                         const int32_t* selcol, const int32_t* cnt_p, double* B,
                                                         int ldb, int* ndropped) {
   __shared__ double M[kMaxL * kMS];
   __shared__ int colpos[kMaxL];
   __shared__ int colid[kMaxL];
+  __shared__ int selrow[kMaxL];
   const int t = threadIdx.x;
   const int r = *cnt_p;
   if (t < kMaxL) colpos[t] = -1;
@@ -234,48 +244,50 @@ __global__ __launch_bounds__(256) void lu_factor_kernel(const float* X, int ldx,
   if (t < r) {
     colid[t] = selcol[t];
     colpos[selcol[t]] = t;
+    selrow[t] = sel[t];
   }
   __syncthreads();
-  if (t < r) {
-    const float* src = X + (size_t)sel[t] * ldx;
-    for (int j = 0; j < r; ++j) M[t * kMS + j] = (double)src[colid[j]];
+  for (int idx = t; idx < r * r; idx += kFT) {
+    const int i = idx / r, j = idx - i * r;
+    M[i * kMS + j] = (double)X[(size_t)selrow[i] * ldx + colid[j]];
   }
   __syncthreads();
-  // Doolittle elimination: after step s, row s holds row s of U
-  for (int s = 0; s < r; ++s) {
-    if (t > s && t < r) {
-      const double f = M[t * kMS + s] / M[s * kMS + s];
-      for (int v = s + 1; v < r; ++v) M[t * kMS + v] -= f * M[s * kMS + v];
+  const int c = t & (kMaxL - 1), g = t >> 7;  // column, row phase 0..7
+  for (int s = 0; s + 1 < r; ++s) {
+    if (t > s && t < r) M[t * kMS + s] /= M[s * kMS + s];
+    __syncthreads();
+    if (c > s && c < r) {
+      const double us = M[s * kMS + c];
+      for (int i = s + 1 + g; i < r; i += 8) M[i * kMS + c] -= M[i * kMS + s] * us;
     }
     __syncthreads();
   }
-  // in-place inverse of the upper triangle, bottom row first: thread j computes T[i][j]
-  for (int i = r - 1; i >= 0; --i) {
-    double val = 0.0;
-    const int j = t;
-    if (j >= i && j < r) {
-      const double dinv = 1.0 / M[i * kMS + i];
-      if (j == i) {
-        val = dinv;
-      } else {
-        double acc = 0.0;
-        for (int k = i + 1; k <= j; ++k) acc += M[i * kMS + k] * M[k * kMS + j];
-        val = -dinv * acc;
+  {
+    const int i = t >> 3, part = t & 7;
+    for (int j = 0; j < r; ++j) {
+      double y = 0.0;
+      if (i < j) {
+        const double* Ti = M + i * kMS;
+        for (int k = i + part; k < j; k += 8) y += Ti[k] * M[k * kMS + j];
       }
+      y += __shfl_xor(y, 1);
+      y += __shfl_xor(y, 2);
+      y += __shfl_xor(y, 4);
+      const double djj = 1.0 / M[j * kMS + j];
+      __syncthreads();  // every read of column j precedes the writes below
+      if (i < j && part == 0) M[i * kMS + j] = -djj * y;
+      if (t == 0) M[j * kMS + j] = djj;
+      __syncthreads();
     }
-    __syncthreads();
-    if (j >= i && j < r) M[i * kMS + j] = val;
-    __syncthreads();
   }
-  for (int a = 0; a < l; ++a) {
-    for (int b = t; b < ldb; b += 256) {
-      double v = 0.0;
-      if (b < l) {
-        const int pa = colpos[a], pb = colpos[b];
-        if (pa >= 0 && pb >= 0 && pa <= pb) v = M[pa * kMS + pb];
-      }
-      B[(size_t)a * ldb + b] = v;
+  for (int idx = t; idx < l * ldb; idx += kFT) {
+    const int a = idx / ldb, b = idx - a * ldb;
+    double v = 0.0;
+    if (b < l) {
+      const int pa = colpos[a], pb = colpos[b];
+      if (pa >= 0 && pb >= 0 && pa <= pb) v = M[pa * kMS + pb];
     }
+    B[idx] = v;
   }
   if (t == 0 && ndropped) *ndropped = l - r;
 }
@@ -339,7 +351,7 @@ void launch_lu_coeffs(const float* X, int ldx, int64_t rows, int l, double tol, 
     cur = 1 - cur;
     nodes = next;
   }
-  lu_factor_kernel<<<1, 256, 0, st>>>(X, ldx, l, sel[cur], col[cur], cnt[cur], B, ldb, ndropped_dev);
+  lu_factor_kernel<<<1, kFT, 0, st>>>(X, ldx, l, sel[cur], col[cur], cnt[cur], B, ldb, ndropped_dev);
 }
 
 }  // namespace frpca
