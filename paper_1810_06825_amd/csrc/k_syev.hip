@@ -54,6 +54,51 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return s;
 }
 
+// Lane l's value, broadcast to the wave (l uniform).
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// DPP move of a double (both halves through the same control); lanes whose source is invalid
+// or whose row is masked off read 0.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROW_MASK, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Sum over each half-wave (lanes 0-31, 32-63), valid in lanes 31 and 63: row shifts 1, 2, 4, 8
+// put each row's sum in its lane 15, then row 0's (row 2's) total is broadcast into row 1 (3).
+__device__ __forceinline__ double half_sum_to_last(double v) {
+  v += dpp64<0x111, 0xF>(v);
+  v += dpp64<0x112, 0xF>(v);
+  v += dpp64<0x114, 0xF>(v);
+  v += dpp64<0x118, 0xF>(v);
+  v += dpp64<0x142, 0xA>(v);
+  return v;
+}
+
+// Sum over each group of 8 lanes, in all 8: quad xor 1, quad xor 2, then lane i + lane 7 - i.
+__device__ __forceinline__ double oct_allsum(double v) {
+  v += dpp64<0xB1, 0xF>(v);
+  v += dpp64<0x4E, 0xF>(v);
+  v += dpp64<0x141, 0xF>(v);
+  return v;
+}
+
+// 1/v to within a few ulps: hardware reciprocal refined by two Newton steps (cheaper than the
+// IEEE division sequence on the serial chains below).
+__device__ __forceinline__ double rcp2(double v) {
+  double r = __builtin_amdgcn_rcp(v);
+  r = fma(fma(-v, r, 1.0), r, r);
+  return fma(fma(-v, r, 1.0), r, r);
+}
+
 __device__ __forceinline__ double guard(double v, double pivmin) {
   return fabs(v) < pivmin ? -pivmin : v;
 }
@@ -70,16 +115,33 @@ __device__ int sturm_T(const double* d, const double* e2, int o, int nb, double 
 }
 
 // Number of eigenvalues of L D L^T (block [o, o+nb)) below x: negative pivots of the
-// stationary qd transform.
+// stationary qd transform. Four steps at a time with their LDS operands fetched first, so the
+// dependent chain does not wait on loads.
+__device__ __forceinline__ void negstep(double& s, int& c, double Di, double LLDi, double x, double pivmin) {
+  const double dp = guard(Di + s, pivmin);
+  c += dp < 0.0;
+  // 1/dp by the hardware reciprocal and two Newton steps (a few ulps at most: the count is
+  // backward stable under such relative perturbations of the representation)
+  s = (s * rcp2(dp)) * LLDi - x;
+}
+
 __device__ int negcount(const double* D, const double* LLD, int o, int nb, double x, double pivmin) {
   double s = -x;
   int c = 0;
-  for (int i = o; i < o + nb - 1; ++i) {
-    const double dp = guard(D[i] + s, pivmin);
-    c += dp < 0.0;
-    s = (s / dp) * LLD[i] - x;
+  const int end = o + nb - 1;
+  int i = o;
+  for (; i + 4 <= end; i += 4) {
+    double d4[4], l4[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      d4[u] = D[i + u];
+      l4[u] = LLD[i + u];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) negstep(s, c, d4[u], l4[u], x, pivmin);
   }
-  c += guard(D[o + nb - 1] + s, pivmin) < 0.0;
+  for (; i < end; ++i) negstep(s, c, D[i], LLD[i], x, pivmin);
+  c += guard(D[end] + s, pivmin) < 0.0;
   return c;
 }
 
@@ -97,38 +159,51 @@ __device__ __forceinline__ double jitter(int g, int i) {
 __global__ __launch_bounds__(kT) void syev_kernel(const double* G, int ldg, int n, double* d_out, double* W,
                                                   double* scratch) {
   __shared__ double A[kMaxL * kS];  // G, then the eigenvectors Z of T
-  __shared__ double d[kMaxL], e[kMaxL], e2[kMaxL], tau[kMaxL], vk[kMaxL], pw[kMaxL];
+  __shared__ double d[kMaxL], e[kMaxL], e2[kMaxL], tau[kMaxL], pw[kMaxL];
   __shared__ double Dr[kMaxL], Lr[kMaxL], LLD[kMaxL], mu[kMaxL], shift[kMaxL];
   __shared__ double bsig[kMaxL], bgl[kMaxL], bgu[kMaxL], btn[kMaxL];
   __shared__ double red[kT / 64], red2[kT / 64];
+  __shared__ double colbuf[kMaxL];
   __shared__ int bstart[kMaxL], bsize[kMaxL], bbad[kMaxL], cl0[kMaxL], incl[kMaxL], rank_s[kMaxL];
+  __shared__ int gs_list[kMaxL];
   __shared__ int sh_int[4];
   __shared__ double sh_dbl[4];
   double* house = scratch;                   // kMaxL x kMaxL reflectors
   double* lwork = scratch + kMaxL * kMaxL;   // per-column L+ of the cluster solves
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int row8 = tid >> 3, sub8 = tid & 7;
-
-  for (int idx = tid; idx < n * n; idx += kT) {
-    const int i = idx / n, j = idx - i * n;
-    A[i * kS + j] = G[(size_t)i * ldg + j];
-  }
-  __syncthreads();
 
   // ---------------------------------------------------------------- 1. tridiagonalization
+  // G in registers: thread t holds the 4 x 4 tile of rows 4 rb.., columns 4 cb.. (rb = t / 32,
+  // cb = t % 32), so a wave holds two tile rows and a half-wave reduction sums over a row.
+  const int rb = tid >> 5, cb = tid & 31;
+  double ta[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int R = 4 * rb + a, C = 4 * cb + b;
+      ta[a][b] = (R < n && C < n) ? G[(size_t)R * ldg + C] : 0.0;
+    }
+  // column 0 into colbuf, with its sum of squares below the subdiagonal (owners: cb == 0)
   {
     double part = 0.0;
-    for (int i = 2 + tid; i < n; i += kT) part += A[i * kS] * A[i * kS];
-    part = wave_sum(part);
-    if (lane == 0) red[wave] = part;
+    if (cb == 0) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const int R = 4 * rb + a;
+        colbuf[R] = ta[a][0];
+        if (R >= 2 && R < n) part += ta[a][0] * ta[a][0];
+      }
+    }
+    const double wpart = readlane_d(part, 0) + readlane_d(part, 32);
+    if (lane == 0) red[wave] = wpart;
   }
   __syncthreads();
   for (int k = 0; k + 2 < n; ++k) {
-    const int m = n - k - 1;
     double sigma = 0.0;
 #pragma unroll
     for (int w = 0; w < kT / 64; ++w) sigma += red[w];
-    const double x0 = A[(k + 1) * kS + k];
+    const double x0 = colbuf[k + 1];
     double tk = 0.0, beta = x0, scal = 0.0;
     if (sigma != 0.0) {
       const double mu0 = sqrt(x0 * x0 + sigma);
@@ -136,59 +211,112 @@ __global__ __launch_bounds__(kT) void syev_kernel(const double* G, int ldg, int 
       tk = (beta - x0) / beta;
       scal = 1.0 / (x0 - beta);
     }
-    for (int i = tid; i < m; i += kT) {
-      const double v = (i == 0) ? 1.0 : A[(k + 1 + i) * kS + k] * scal;
-      vk[i] = v;
-      house[(size_t)k * kMaxL + i] = v;
-    }
     if (tid == 0) {
       tau[k] = tk;
       e[k] = beta;
-      d[k] = A[k * kS + k];
     }
-    __syncthreads();  // (1)
-    double acc = 0.0;
-    if (row8 < m) {
-      const double* ar = A + (k + 1 + row8) * kS + (k + 1);
-      for (int j = sub8; j < m; j += 8) acc += ar[j] * vk[j];
+    if (rb == (k >> 2) && cb == (k >> 2)) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+        if (a == (k & 3)) d[k] = ta[a][a];
     }
-    acc += __shfl_xor(acc, 1);
-    acc += __shfl_xor(acc, 2);
-    acc += __shfl_xor(acc, 4);
-    const double pr = tk * acc;
-    if (row8 < m && sub8 == 0) pw[row8] = pr;
-    double pv = (row8 < m && sub8 == 0) ? pr * vk[row8] : 0.0;
-    pv = wave_sum(pv);
-    if (lane == 0) red2[wave] = pv;
-    __syncthreads();  // (2)
+    // waves whose two tile rows lie above the trailing block have nothing to do this step
+    const bool wact = 8 * wave + 7 >= k + 1;
+    double vr[4], vc[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int R = 4 * rb + a, C = 4 * cb + a;
+      vr[a] = (R == k + 1) ? 1.0 : ((R > k + 1 && R < n) ? colbuf[R] * scal : 0.0);
+      vc[a] = (C == k + 1) ? 1.0 : ((C > k + 1 && C < n) ? colbuf[C] * scal : 0.0);
+    }
+    // v_k is kept in row k of the LDS matrix, which is free during this phase (a global store
+    // here would make every barrier wait for it)
+    if (cb == 0) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const int R = 4 * rb + a;
+        if (R >= k + 1 && R < n) A[k * kS + (R - k - 1)] = vr[a];
+      }
+    }
+    // p = tau A22 v on the own rows: partial over the own columns, summed over the half-wave
+    double pp[4] = {0.0, 0.0, 0.0, 0.0};
+    if (wact) {  // uniform per wave: the DPP sums need every lane
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        double acc = 0.0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc += ta[a][b] * vc[b];
+        pp[a] = half_sum_to_last(acc);
+      }
+    }
+    double pvp = 0.0;
+    if (wact && cb == 31) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const int R = 4 * rb + a;
+        if (R >= k + 1 && R < n) {
+          const double pr = tk * pp[a];
+          pw[R] = pr;
+          pvp += pr * vr[a];
+        }
+      }
+    }
+    const double wpv = readlane_d(pvp, 31) + readlane_d(pvp, 63);
+    if (lane == 0) red2[wave] = wpv;
+    __syncthreads();  // (A)
     double K = 0.0;
 #pragma unroll
     for (int w = 0; w < kT / 64; ++w) K += red2[w];
     K *= 0.5 * tk;
+    if (wact) {
+      double wr[4], wc[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const int R = 4 * rb + a, C = 4 * cb + a;
+        wr[a] = (R >= k + 1 && R < n) ? pw[R] - K * vr[a] : 0.0;
+        wc[a] = (C >= k + 1 && C < n) ? pw[C] - K * vc[a] : 0.0;
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) ta[a][b] -= vr[a] * wc[b] + wr[a] * vc[b];
+    }
+    // column k+1 into colbuf and the next step's sum of squares (owners: cb == (k+1)/4)
+    const int cbn = (k + 1) >> 2, bn = (k + 1) & 3;
     double part = 0.0;
-    if (row8 < m) {
-      const double vi = vk[row8], wi = pr - K * vi;
-      double* ar = A + (k + 1 + row8) * kS + (k + 1);
-      for (int j = sub8; j < m; j += 8) {
-        const double vj = vk[j];
-        const double a = ar[j] - (vi * (pw[j] - K * vj) + wi * vj);
-        ar[j] = a;
-        if (j == 0 && row8 >= 2) part += a * a;
+    if (cb == cbn) {
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        if (b == bn) {
+#pragma unroll
+          for (int a = 0; a < 4; ++a) {
+            const int R = 4 * rb + a;
+            colbuf[R] = ta[a][b];
+            if (R >= k + 3 && R < n) part += ta[a][b] * ta[a][b];
+          }
+        }
       }
     }
-    part = wave_sum(part);
-    if (lane == 0) red[wave] = part;
-    __syncthreads();  // (3)
+    const double wpart = readlane_d(part, cbn) + readlane_d(part, 32 + cbn);
+    if (lane == 0) red[wave] = wpart;
+    __syncthreads();  // (B)
   }
-  if (tid == 0) {
-    if (n >= 2) {
-      d[n - 2] = A[(n - 2) * kS + (n - 2)];
-      e[n - 2] = A[(n - 1) * kS + (n - 2)];
+  // the last 2 x 2 block
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int R = 4 * rb + a, C = 4 * cb + b;
+      if (R == C && R >= n - 2 && R >= 0 && R < n) d[R] = ta[a][b];
+      if (n >= 2 && R == n - 1 && C == n - 2) e[n - 2] = ta[a][b];
     }
-    d[n - 1] = A[(n - 1) * kS + (n - 1)];
-    e[n - 1] = 0.0;
-  }
+  if (tid == 0) e[n - 1] = 0.0;
   __syncthreads();
+  // the reflectors move to global scratch until the back-transformation
+  for (int idx = tid; idx < (n - 2) * kMaxL; idx += kT) {
+    const int k = idx / kMaxL, i = idx - k * kMaxL;
+    if (i < n - k - 1) house[idx] = A[k * kS + i];
+  }
 
   // ---------------------------------------------------------------- 2. blocks and root representations
   if (tid == 0) {
@@ -290,8 +418,11 @@ __global__ __launch_bounds__(kT) void syev_kernel(const double* G, int ldg, int 
   }
 
   // ---------------------------------------------------------------- 3. eigenvalues of L D L^T
+  // Four lanes per eigenvalue (five subintervals per step) on the first eight waves: the
+  // counts are bound by FP64 issue, and this split balances the work against the latency of
+  // each lane's serial chain.
   {
-    const int g = row8;
+    const int g = tid >> 2, sub = tid & 3;
     const bool act = g < n && bsize[g] > 1;
     int o = 0, nb = 1, want = 0;
     double lo = 0.0, hi = 0.0;
@@ -301,37 +432,37 @@ __global__ __launch_bounds__(kT) void syev_kernel(const double* G, int ldg, int 
       want = g - o;
       hi = (bgu[o] - bsig[o]) + 4.0 * nb * kEps * fmax(btn[o], fabs(bsig[o])) + pivmin;
     }
-    for (int it = 0; it < 64; ++it) {
+    for (int it = 0; it < 96; ++it) {
       const bool busy = act && !(lo > 0.0 && hi - lo <= 4.0 * kEps * hi);
-      if (!__any(busy)) break;  // per wave; the eight lanes of a group agree on busy
+      if (!__any(busy)) break;  // per wave; the four lanes of a group agree on busy
       double x;
       if (lo == 0.0) {
-        x = ldexp(hi, -7 * (8 - sub8));
+        x = ldexp(hi, -14 * (4 - sub));
       } else if (hi > 1.5 * lo) {
-        x = lo * exp2(log2(hi / lo) * (double)(sub8 + 1) / 9.0);
+        x = lo * exp2(log2(hi / lo) * (double)(sub + 1) / 5.0);
       } else {
-        x = lo + (hi - lo) * (double)(sub8 + 1) / 9.0;
+        x = lo + (hi - lo) * (double)(sub + 1) / 5.0;
       }
       x = fmin(fmax(x, lo), hi);
       const int c = busy ? negcount(Dr, LLD, o, nb, x, pivmin) : 0;
-      int b = 8;
+      int b = 4;
       double xb = hi, xb1 = lo;
 #pragma unroll
-      for (int s = 0; s < 8; ++s) {
-        const int cs = __shfl(c, (lane & ~7) + s);
-        const double xs = __shfl(x, (lane & ~7) + s);
-        if (b == 8 && cs > want) {
-          b = s;
+      for (int q = 0; q < 4; ++q) {
+        const int cs = __shfl(c, (lane & ~3) + q);
+        const double xs = __shfl(x, (lane & ~3) + q);
+        if (b == 4 && cs > want) {
+          b = q;
           xb = xs;
         }
-        if (b == 8) xb1 = xs;
+        if (b == 4) xb1 = xs;
       }
       if (busy) {
         lo = xb1;
         hi = xb;
       }
     }
-    if (sub8 == 0 && g < n) mu[g] = act ? 0.5 * (lo + hi) : 0.0;
+    if (sub == 0 && g < n) mu[g] = act ? 0.5 * (lo + hi) : 0.0;
   }
   __syncthreads();
 
@@ -359,7 +490,7 @@ __global__ __launch_bounds__(kT) void syev_kernel(const double* G, int ldg, int 
       for (int i = o; i < last; ++i) {
         z[i * kS] = s;
         const double dp = guard(Dr[i] + s, pivmin);
-        s = (Dr[i] * Lr[i] / dp) * Lr[i] * s - lam;
+        s = (Dr[i] * Lr[i] * rcp2(dp)) * Lr[i] * s - lam;
       }
       z[last * kS] = s;
       // progressive transform bottom-up: gamma_i = s_i + p_i + lam, U-_i into z
@@ -368,7 +499,7 @@ __global__ __launch_bounds__(kT) void syev_kernel(const double* G, int ldg, int 
       double gbest = fabs(z[last * kS] + p + lam);
       for (int i = last - 1; i >= o; --i) {
         const double dm = guard(LLD[i] + p, pivmin);
-        const double t = Dr[i] / dm;
+        const double t = Dr[i] * rcp2(dm);
         const double um = Lr[i] * t;
         p = p * t - lam;
         const double gam = fabs(z[i * kS] + p + lam);
@@ -382,7 +513,7 @@ __global__ __launch_bounds__(kT) void syev_kernel(const double* G, int ldg, int 
       s = -lam;
       for (int i = o; i < r; ++i) {
         const double dp = guard(Dr[i] + s, pivmin);
-        const double lp = Dr[i] * Lr[i] / dp;
+        const double lp = Dr[i] * Lr[i] * rcp2(dp);
         z[i * kS] = lp;
         s = lp * Lr[i] * s - lam;
       }
@@ -431,12 +562,17 @@ __global__ __launch_bounds__(kT) void syev_kernel(const double* G, int ldg, int 
     }
   }
   if (tid == 0) {
-    int any = 0;
-    for (int g = 0; g < n; ++g) any |= incl[g];
+    int any = 0, ngs = 0;
+    for (int g = 0; g < n; ++g) {
+      any |= incl[g];
+      if (incl[g] && cl0[g] < g) gs_list[ngs++] = g;
+    }
     sh_int[1] = any;
+    sh_int[2] = ngs;
   }
   __syncthreads();
   if (sh_int[1]) {
+    const int ngs = sh_int[2];
     for (int it = 0; it < kClusterIters; ++it) {
       // (L D L^T - shift I) y = z for every clustered column, in place
       if (tid < n && incl[tid]) {
@@ -447,24 +583,34 @@ __global__ __launch_bounds__(kT) void syev_kernel(const double* G, int ldg, int 
         const double pfl = fmax(kEps * lam, pivmin);
         double* z = A + g;
         double* lp = lwork + (size_t)g * kMaxL;
-        double s = -lam, yprev = 0.0;
+        double s = -lam, yprev = 0.0, lprev = 0.0;
         for (int i = o; i <= last; ++i) {
           const double dp = guard(Dr[i] + s, pfl);
-          const double y = z[i * kS] - ((i > o) ? lp[i - 1] * yprev : 0.0);
+          const double rp = rcp2(dp);
+          const double y = z[i * kS] - lprev * yprev;
           yprev = y;
-          z[i * kS] = y / dp;
+          z[i * kS] = y * rp;
           if (i < last) {
-            const double l = Dr[i] * Lr[i] / dp;
-            lp[i] = l;
-            s = l * Lr[i] * s - lam;
+            lprev = Dr[i] * Lr[i] * rp;
+            lp[i] = lprev;
+            s = lprev * Lr[i] * s - lam;
           }
         }
         double ynext = z[last * kS], ymax = fabs(ynext);
-        for (int i = last - 1; i >= o; --i) {
-          const double y = z[i * kS] - lp[i] * ynext;
-          z[i * kS] = y;
-          ynext = y;
-          ymax = fmax(ymax, fabs(y));
+        for (int i = last - 1; i >= o; i -= 8) {
+          // the L+ values come from global memory: fetch eight before the dependent chain
+          double lv[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) lv[u] = (i - u >= o) ? lp[i - u] : 0.0;
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            if (i - u >= o) {
+              const double y = z[(i - u) * kS] - lv[u] * ynext;
+              z[(i - u) * kS] = y;
+              ynext = y;
+              ymax = fmax(ymax, fabs(y));
+            }
+          }
         }
         if (ymax > 0.0) {  // scale first: the solve output can be far from 1 in magnitude
           const double sc = 1.0 / ymax;
@@ -479,9 +625,8 @@ __global__ __launch_bounds__(kT) void syev_kernel(const double* G, int ldg, int 
         }
       }
       __syncthreads();
-      for (int g = 0; g < n; ++g) {
-        const int c0 = cl0[g];
-        if (!incl[g] || c0 == g) continue;  // uniform
+      for (int gi = 0; gi < ngs; ++gi) {
+        const int g = gs_list[gi], c0 = cl0[g];
         for (int pass = 0; pass < 2; ++pass) {
           for (int i = c0 + wave; i < g; i += kT / 64) {
             double s = 0.0;
@@ -505,25 +650,6 @@ __global__ __launch_bounds__(kT) void syev_kernel(const double* G, int ldg, int 
     }
   }
 
-  // ---------------------------------------------------------------- 5. back-transformation
-  for (int k = n - 3; k >= 0; --k) {
-    const int m = n - k - 1;
-    for (int i = tid; i < m; i += kT) vk[i] = house[(size_t)k * kMaxL + i];
-    __syncthreads();
-    const double tk = tau[k];
-    double s = 0.0;
-    if (row8 < n && tk != 0.0)
-      for (int i = sub8; i < m; i += 8) s += vk[i] * A[(k + 1 + i) * kS + row8];
-    s += __shfl_xor(s, 1);
-    s += __shfl_xor(s, 2);
-    s += __shfl_xor(s, 4);
-    if (row8 < n && tk != 0.0) {
-      const double ts = tk * s;
-      for (int i = sub8; i < m; i += 8) A[(k + 1 + i) * kS + row8] -= ts * vk[i];
-    }
-    __syncthreads();
-  }
-
   // ---------------------------------------------------------------- eigenvalues ascending
   if (tid < n) {
     const int g = tid, o = bstart[g];
@@ -541,10 +667,43 @@ __global__ __launch_bounds__(kT) void syev_kernel(const double* G, int ldg, int 
     rank_s[tid] = r;
     d_out[r] = v;
   }
+
+  // ---------------------------------------------------------------- 5. back-transformation
+  // Z into registers: wave w owns columns 8w..8w+7; lane L holds column 8w + L/8, rows
+  // 16 (L%8) .. 16 (L%8) + 15. The reflectors then move into the freed LDS matrix (row k holds
+  // v_k for rows k+1..n-1), and every wave applies all of them to its own columns with no
+  // further barrier: s = v^T z summed over the eight lanes of a column, z -= tau s v.
+  const int zc = 8 * wave + (lane >> 3), zr0 = 16 * (lane & 7);
+  double z[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) z[q] = (zr0 + q < n && zc < n) ? A[(zr0 + q) * kS + zc] : 0.0;
   __syncthreads();
-  for (int idx = tid; idx < n * n; idx += kT) {
-    const int i = idx / n, g = idx - i * n;
-    W[(size_t)i * n + rank_s[g]] = A[i * kS + g];
+  for (int idx = tid; idx < (n - 2) * kMaxL; idx += kT) {
+    const int k = idx / kMaxL, i = idx - k * kMaxL;
+    if (i < n - k - 1) A[k * kS + i] = house[idx];
+  }
+  __syncthreads();
+  for (int k = n - 3; k >= 0; --k) {
+    const double tk = tau[k];
+    if (tk == 0.0) continue;  // uniform
+    const double* hv = A + k * kS;
+    double vq[16];
+    double sp = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int row = zr0 + q;
+      vq[q] = (row >= k + 1 && row < n) ? hv[row - k - 1] : 0.0;
+      sp += vq[q] * z[q];
+    }
+    const double ts = tk * oct_allsum(sp);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) z[q] -= ts * vq[q];
+  }
+  if (zc < n) {
+    const int col = rank_s[zc];
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+      if (zr0 + q < n) W[(size_t)(zr0 + q) * n + col] = z[q];
   }
 }
 
