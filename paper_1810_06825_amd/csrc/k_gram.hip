@@ -18,8 +18,10 @@ namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
+constexpr int kGramThreads = 512;  // 8 waves: 4 groups of tile pairs x 2 interleaved row streams
 constexpr int kGramMaxBlocks = 512;
-constexpr int kMaxPairs = 64;  // 8 x 8 tiles
+constexpr int kMaxPairs = 64;      // 8 x 8 tiles
+constexpr int kRedPart = 4;        // block-sum interleave of the reduction
 
 template <int B, int E, class F>
 __device__ __forceinline__ void static_for(F&& f) {
@@ -49,66 +51,140 @@ constexpr int pair_j(int nt, bool sym, int p) {
 }
 constexpr int npairs(int nt, bool sym) { return sym ? nt * (nt + 1) / 2 : nt * nt; }
 
-template <int NT, bool SYM, int WAVE>
-__device__ __forceinline__ void gram_wave(const float* X1, int ld1, const float* X2, int ld2, int64_t r0,
-                                          int64_t r1, int l, double* out) {
+// Column order inside the tiles: groups of four tiles cover 64 consecutive columns (entry t of
+// tile I is column 64 (I/4) + 4t + I%4) and a trailing pair covers 32 (entry t of tile I is
+// 64 G4 + 2t + (I - 4 G4)), so a lane's operands for all tiles come from one 16-byte (or
+// 8-byte) load per group. The reduction maps the tiles back.
+__host__ __device__ constexpr int gram_col(int nt, int I, int t) {
+  return (I < 4 * (nt / 4)) ? 64 * (I / 4) + 4 * t + (I % 4) : 64 * (nt / 4) + 2 * t + (I - 4 * (nt / 4));
+}
+
+template <int NT>
+__device__ __forceinline__ void gram_load(const float* X, int ld, int64_t row, bool ok, int l, int cc, bool vec,
+                                          float v[NT]) {
+  constexpr int G4 = NT / 4;
+#pragma unroll
+  for (int g = 0; g < G4; ++g) {
+    const int c0 = 64 * g + 4 * cc;
+    if (ok && vec && c0 + 3 < l) {
+      const float4 w = *reinterpret_cast<const float4*>(X + (size_t)row * ld + c0);
+      v[4 * g] = w.x;
+      v[4 * g + 1] = w.y;
+      v[4 * g + 2] = w.z;
+      v[4 * g + 3] = w.w;
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v[4 * g + q] = (ok && c0 + q < l) ? X[(size_t)row * ld + c0 + q] : 0.f;
+    }
+  }
+  if constexpr (NT % 4 != 0) {
+    const int c0 = 64 * G4 + 2 * cc;
+    if (ok && vec && c0 + 1 < l) {
+      const float2 w = *reinterpret_cast<const float2*>(X + (size_t)row * ld + c0);
+      v[4 * G4] = w.x;
+      v[4 * G4 + 1] = w.y;
+    } else {
+#pragma unroll
+      for (int q = 0; q < 2; ++q) v[4 * G4 + q] = (ok && c0 + q < l) ? X[(size_t)row * ld + c0 + q] : 0.f;
+    }
+  }
+}
+
+template <int NT, bool SYM, int PG>
+__device__ __forceinline__ void gram_wave(const float* X1, int ld1, const float* X2, int ld2, bool vec, int64_t r0,
+                                          int64_t r1, int half, int l, double* out, double* lds) {
   constexpr int NP = npairs(NT, SYM);
-  constexpr int PPW = (NP - WAVE + 3) / 4;  // pairs p = WAVE + 4q
+  constexpr int PPW = (NP - PG + 3) / 4;  // pairs p = PG + 4q
   const int lane = threadIdx.x & 63;
   const int kr = lane >> 4, cc = lane & 15;
   d4 acc[PPW > 0 ? PPW : 1];
 #pragma unroll
   for (int q = 0; q < (PPW > 0 ? PPW : 1); ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
-  for (int64_t r = r0; r < r1; r += 4) {
-    const int64_t rr = r + kr;
-    const bool ok = rr < r1;
+  float na[NT], nb[NT];
+  int64_t r = r0 + 4 * half;
+  if (r < r1) {
+    gram_load<NT>(X1, ld1, r + kr, r + kr < r1, l, cc, vec, na);
+    if constexpr (!SYM) gram_load<NT>(X2, ld2, r + kr, r + kr < r1, l, cc, vec, nb);
+  }
+  for (; r < r1; r += 8) {
     double a[NT], b[NT];
 #pragma unroll
     for (int I = 0; I < NT; ++I) {
-      const int c = 16 * I + cc;
-      a[I] = (ok && c < l) ? (double)X1[rr * ld1 + c] : 0.0;
-      if constexpr (!SYM) b[I] = (ok && c < l) ? (double)X2[rr * ld2 + c] : 0.0;
+      a[I] = (double)na[I];
+      if constexpr (!SYM) b[I] = (double)nb[I];
+    }
+    // the next step's rows load while this step's MFMAs run
+    const int64_t rn = r + 8;
+    if (rn < r1) {
+      gram_load<NT>(X1, ld1, rn + kr, rn + kr < r1, l, cc, vec, na);
+      if constexpr (!SYM) gram_load<NT>(X2, ld2, rn + kr, rn + kr < r1, l, cc, vec, nb);
     }
     static_for<0, PPW>([&](auto qc) {
-      constexpr int p = WAVE + 4 * decltype(qc)::value;
+      constexpr int p = PG + 4 * decltype(qc)::value;
       constexpr int I = pair_i(NT, SYM, p), J = pair_j(NT, SYM, p);
       if constexpr (SYM) acc[qc] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[I], a[J], acc[qc], 0, 0, 0);
       else acc[qc] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[I], b[J], acc[qc], 0, 0, 0);
     });
   }
-  static_for<0, PPW>([&](auto qc) {
-    constexpr int p = WAVE + 4 * decltype(qc)::value;
-    double* o = out + (size_t)p * 256 + lane * 4;
-    o[0] = acc[qc][0];
-    o[1] = acc[qc][1];
-    o[2] = acc[qc][2];
-    o[3] = acc[qc][3];
-  });
-}
-
-template <int NT, bool SYM>
-__global__ __launch_bounds__(256) void gram_kernel(const float* X1, int ld1, const float* X2, int ld2,
-                                                   int64_t rows, int l, int64_t rows_per_block, double* partial) {
-  constexpr int NP = npairs(NT, SYM);
-  const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
-  const int64_t r1 = min(rows, r0 + rows_per_block);
-  double* out = partial + (size_t)blockIdx.x * NP * 256;
-  switch (threadIdx.x >> 6) {
-    case 0: gram_wave<NT, SYM, 0>(X1, ld1, X2, ld2, r0, r1, l, out); break;
-    case 1: gram_wave<NT, SYM, 1>(X1, ld1, X2, ld2, r0, r1, l, out); break;
-    case 2: gram_wave<NT, SYM, 2>(X1, ld1, X2, ld2, r0, r1, l, out); break;
-    default: gram_wave<NT, SYM, 3>(X1, ld1, X2, ld2, r0, r1, l, out); break;
+  // the two row streams combine in LDS (second stream first, fixed order)
+  if (half == 1) {
+    static_for<0, PPW>([&](auto qc) {
+      double* o = lds + ((size_t)(PG + 4 * decltype(qc)::value) * 64 + lane) * 4;
+      o[0] = acc[qc][0];
+      o[1] = acc[qc][1];
+      o[2] = acc[qc][2];
+      o[3] = acc[qc][3];
+    });
+  }
+  __syncthreads();
+  if (half == 0) {
+    static_for<0, PPW>([&](auto qc) {
+      constexpr int p = PG + 4 * decltype(qc)::value;
+      const double* i2 = lds + ((size_t)p * 64 + lane) * 4;
+      double* o = out + (size_t)p * 256 + lane * 4;
+      o[0] = acc[qc][0] + i2[0];
+      o[1] = acc[qc][1] + i2[1];
+      o[2] = acc[qc][2] + i2[2];
+      o[3] = acc[qc][3] + i2[3];
+    });
   }
 }
 
+template <int NT, bool SYM>
+__global__ __launch_bounds__(kGramThreads) void gram_kernel(const float* X1, int ld1, const float* X2, int ld2,
+                                                            int vec, int64_t rows, int l, int64_t rows_per_block,
+                                                            double* partial) {
+  constexpr int NP = npairs(NT, SYM);
+  __shared__ double lds[NP * 256];
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+  const int64_t r1 = min(rows, r0 + rows_per_block);
+  double* out = partial + (size_t)blockIdx.x * NP * 256;
+  const int w = threadIdx.x >> 6, half = w >> 2;
+  switch (w & 3) {
+    case 0: gram_wave<NT, SYM, 0>(X1, ld1, X2, ld2, vec != 0, r0, r1, half, l, out, lds); break;
+    case 1: gram_wave<NT, SYM, 1>(X1, ld1, X2, ld2, vec != 0, r0, r1, half, l, out, lds); break;
+    case 2: gram_wave<NT, SYM, 2>(X1, ld1, X2, ld2, vec != 0, r0, r1, half, l, out, lds); break;
+    default: gram_wave<NT, SYM, 3>(X1, ld1, X2, ld2, vec != 0, r0, r1, half, l, out, lds); break;
+  }
+}
+
+// Sum of the block partials: 64 consecutive entries per workgroup, four interleaved block
+// streams per entry (stream s adds blocks s, s+4, ... in order), combined in a fixed order;
+// then the entry goes to its place in G (tile columns mapped back, both triangles for SYM).
 __global__ __launch_bounds__(256) void gram_reduce_kernel(const double* partial, int nblk, int nt, bool sym,
                                                           int l, double* G, int ldg) {
+  __shared__ double red[kRedPart][64];
   const int np = sym ? nt * (nt + 1) / 2 : nt * nt;
-  const int idx = blockIdx.x * 256 + threadIdx.x;
-  if (idx >= np * 256) return;
-  const int p = idx >> 8, t = idx & 255, lane = t >> 2, r = t & 3;
+  const int e = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int part = threadIdx.x >> 6;
   double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += partial[((size_t)b * np + p) * 256 + t];
+  if (e < np * 256)
+    for (int b = part; b < nblk; b += kRedPart) s += partial[(size_t)b * np * 256 + e];
+  red[part][threadIdx.x & 63] = s;
+  __syncthreads();
+  if (part != 0 || e >= np * 256) return;
+  s = (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
+  const int p = e >> 8, t = e & 255, lane = t >> 2, r = t & 3;
   int I, J;
   if (sym) {
     int q = p;
@@ -122,8 +198,8 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(const double* partial,
     I = p / nt;
     J = p % nt;
   }
-  const int i = 16 * I + (lane >> 4) + 4 * r;
-  const int j = 16 * J + (lane & 15);
+  const int i = gram_col(nt, I, (lane >> 4) + 4 * r);
+  const int j = gram_col(nt, J, lane & 15);
   if (i >= l || j >= l) return;
   if (sym) {
     if (I == J && i > j) return;
@@ -135,13 +211,13 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(const double* partial,
 }
 
 template <bool SYM>
-void gram_dispatch(int nt, unsigned grid, const float* X1, int ld1, const float* X2, int ld2, int64_t rows, int l,
-                   int64_t rpb, double* partial, hipStream_t st) {
+void gram_dispatch(int nt, unsigned grid, const float* X1, int ld1, const float* X2, int ld2, int vec, int64_t rows,
+                   int l, int64_t rpb, double* partial, hipStream_t st) {
   switch (nt) {
-    case 2: gram_kernel<2, SYM><<<grid, 256, 0, st>>>(X1, ld1, X2, ld2, rows, l, rpb, partial); break;
-    case 4: gram_kernel<4, SYM><<<grid, 256, 0, st>>>(X1, ld1, X2, ld2, rows, l, rpb, partial); break;
-    case 6: gram_kernel<6, SYM><<<grid, 256, 0, st>>>(X1, ld1, X2, ld2, rows, l, rpb, partial); break;
-    default: gram_kernel<8, SYM><<<grid, 256, 0, st>>>(X1, ld1, X2, ld2, rows, l, rpb, partial); break;
+    case 2: gram_kernel<2, SYM><<<grid, kGramThreads, 0, st>>>(X1, ld1, X2, ld2, vec, rows, l, rpb, partial); break;
+    case 4: gram_kernel<4, SYM><<<grid, kGramThreads, 0, st>>>(X1, ld1, X2, ld2, vec, rows, l, rpb, partial); break;
+    case 6: gram_kernel<6, SYM><<<grid, kGramThreads, 0, st>>>(X1, ld1, X2, ld2, vec, rows, l, rpb, partial); break;
+    default: gram_kernel<8, SYM><<<grid, kGramThreads, 0, st>>>(X1, ld1, X2, ld2, vec, rows, l, rpb, partial); break;
   }
 }
 
@@ -154,16 +230,18 @@ void launch_gram(const void* X1, bool /*bf16*/, int ld1, const float* X2, int ld
   int nt = (l + 15) / 16;
   nt += nt & 1;
   const bool sym = (X2 == nullptr);
-  int64_t grid = (rows + 63) / 64;
+  const float* x1 = static_cast<const float*>(X1);
+  auto aligned = [](const float* x, int ld) { return (ld % 4) == 0 && (reinterpret_cast<uintptr_t>(x) % 16) == 0; };
+  const int vec = aligned(x1, ld1) && (sym || aligned(X2, ld2));
+  int64_t grid = (rows + 127) / 128;
   if (grid > kGramMaxBlocks) grid = kGramMaxBlocks;
   if (grid < 1) grid = 1;
   int64_t rpb = (rows + grid - 1) / grid;
-  rpb = (rpb + 3) / 4 * 4;
-  const float* x1 = static_cast<const float*>(X1);
-  if (sym) gram_dispatch<true>(nt, (unsigned)grid, x1, ld1, x1, ld1, rows, l, rpb, partial, st);
-  else gram_dispatch<false>(nt, (unsigned)grid, x1, ld1, X2, ld2, rows, l, rpb, partial, st);
+  rpb = (rpb + 7) / 8 * 8;
+  if (sym) gram_dispatch<true>(nt, (unsigned)grid, x1, ld1, x1, ld1, vec, rows, l, rpb, partial, st);
+  else gram_dispatch<false>(nt, (unsigned)grid, x1, ld1, X2, ld2, vec, rows, l, rpb, partial, st);
   const int np = sym ? nt * (nt + 1) / 2 : nt * nt;
-  gram_reduce_kernel<<<(unsigned)((np * 256 + 255) / 256), 256, 0, st>>>(partial, (int)grid, nt, sym, l, G, ldg);
+  gram_reduce_kernel<<<(unsigned)((np * 256 + 63) / 64), 256, 0, st>>>(partial, (int)grid, nt, sym, l, G, ldg);
 }
 
 }  // namespace frpca

@@ -14,6 +14,11 @@ namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
+// 8 waves per block share one copy of B in LDS (up to 133 KB, so one block per CU): two waves
+// per SIMD hide the panel-load latency behind the other's MFMAs.
+constexpr int kTsmmThreads = 512;
+constexpr int kTsmmWaves = kTsmmThreads / 64;
+
 struct TsmmArgs {
   const void* X;
   int ldx;
@@ -28,15 +33,52 @@ struct TsmmArgs {
   uint16_t* out_bf16;
   int ldo16;
   int accumulate;
+  int vec;    // rows of X allow 4-wide vector loads
 };
 
+// k is visited in groups of 16: lane l (group j = l/16, row lr = l%16) loads the four
+// consecutive entries X[r0 + lr][16u + 4j .. 16u + 4j + 3] with one vector load and feeds them
+// to four k-steps (v = 0..3); k-step (u, v) covers k = 16u + 4j + v over j, and the B operand
+// lane supplies B[16u + 4j + v][16 jc + lr] from LDS. The next tile's row slab is fetched
+// into registers while the current tile's MFMAs run.
+template <bool BF16>
+__device__ __forceinline__ void load4(const TsmmArgs& a, int64_t row, int k0, float v[4]) {
+  const bool rok = row < a.rows;
+  if (a.vec && rok && k0 + 3 < a.kdim) {
+    if constexpr (BF16) {
+      const uint2 w = *reinterpret_cast<const uint2*>(static_cast<const uint16_t*>(a.X) + (size_t)row * a.ldx + k0);
+      v[0] = bf16_to_f32((uint16_t)(w.x & 0xFFFF));
+      v[1] = bf16_to_f32((uint16_t)(w.x >> 16));
+      v[2] = bf16_to_f32((uint16_t)(w.y & 0xFFFF));
+      v[3] = bf16_to_f32((uint16_t)(w.y >> 16));
+    } else {
+      const float4 w = *reinterpret_cast<const float4*>(static_cast<const float*>(a.X) + (size_t)row * a.ldx + k0);
+      v[0] = w.x;
+      v[1] = w.y;
+      v[2] = w.z;
+      v[3] = w.w;
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      float x = 0.f;
+      if (rok && k0 + q < a.kdim) {
+        if constexpr (BF16) x = bf16_to_f32(static_cast<const uint16_t*>(a.X)[(size_t)row * a.ldx + k0 + q]);
+        else x = static_cast<const float*>(a.X)[(size_t)row * a.ldx + k0 + q];
+      }
+      v[q] = x;
+    }
+  }
+}
+
 template <int NKT, int NCT, bool BF16>
-__global__ __launch_bounds__(256) void tsmm_kernel(TsmmArgs a) {
+__global__ __launch_bounds__(kTsmmThreads) void tsmm_kernel(TsmmArgs a) {
   constexpr int KP = NKT * 4;
+  constexpr int NU = KP / 16;     // groups of 16 k
   constexpr int CP = NCT * 16;
   constexpr int LDS_LD = CP + 2;  // pad rows so the 4 k-rows of an operand fetch use distinct banks
   __shared__ double Bs[KP * LDS_LD];
-  for (int i = threadIdx.x; i < KP * CP; i += 256) {
+  for (int i = threadIdx.x; i < KP * CP; i += kTsmmThreads) {
     const int r = i / CP, cc = i - r * CP;
     Bs[r * LDS_LD + cc] = (r < a.kdim && cc < a.c) ? a.B[(size_t)r * a.ldb + cc] : 0.0;
   }
@@ -44,25 +86,35 @@ __global__ __launch_bounds__(256) void tsmm_kernel(TsmmArgs a) {
   const int lane = threadIdx.x & 63;
   const int lr = lane & 15, lk = lane >> 4;
   const int64_t ntiles = (a.rows + 15) / 16;
-  const int64_t wstride = (int64_t)gridDim.x * 4;
-  for (int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); tile < ntiles; tile += wstride) {
+  const int64_t wstride = (int64_t)gridDim.x * kTsmmWaves;
+  int64_t tile = (int64_t)blockIdx.x * kTsmmWaves + (threadIdx.x >> 6);
+  float xs[NU][4];
+  if (tile < ntiles) {
+#pragma unroll
+    for (int u = 0; u < NU; ++u) load4<BF16>(a, tile * 16 + lr, 16 * u + 4 * lk, xs[u]);
+  }
+  for (; tile < ntiles; tile += wstride) {
     const int64_t r0 = tile * 16;
-    const int64_t ra = r0 + lr;
-    const bool rok = ra < a.rows;
+    const int64_t nxt = tile + wstride;
     d4 acc[NCT];
 #pragma unroll
     for (int j = 0; j < NCT; ++j) acc[j] = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-    for (int t = 0; t < NKT; ++t) {
-      const int k = 4 * t + lk;
-      double av = 0.0;
-      if (rok && k < a.kdim) {
-        if constexpr (BF16) av = (double)bf16_to_f32(static_cast<const uint16_t*>(a.X)[(size_t)ra * a.ldx + k]);
-        else av = (double)static_cast<const float*>(a.X)[(size_t)ra * a.ldx + k];
-      }
-      const double* brow = Bs + k * LDS_LD + lr;
 #pragma unroll
-      for (int j = 0; j < NCT; ++j) acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, brow[16 * j], acc[j], 0, 0, 0);
+    for (int u = 0; u < NU; ++u) {
+      double av[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) av[v] = (double)xs[u][v];
+      // this group's registers now refill with the next tile's slab
+      if (nxt < ntiles) load4<BF16>(a, nxt * 16 + lr, 16 * u + 4 * lk, xs[u]);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double* brow = Bs + (16 * u + 4 * lk + v) * LDS_LD + lr;
+#pragma unroll
+        for (int j = 0; j < NCT; ++j) acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[v], brow[16 * j], acc[j], 0, 0, 0);
+      }
+      // keep each group's LDS operand reads next to their MFMAs (hoisting them all would
+      // exhaust the register file)
+      __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
     for (int j = 0; j < NCT; ++j) {
@@ -87,20 +139,21 @@ __global__ __launch_bounds__(256) void tsmm_kernel(TsmmArgs a) {
 template <int NKT, bool BF16>
 void tsmm_dispatch_c(int nct, unsigned grid, const TsmmArgs& a, hipStream_t st) {
   switch (nct) {
-    case 1: tsmm_kernel<NKT, 1, BF16><<<grid, 256, 0, st>>>(a); break;
-    case 2: tsmm_kernel<NKT, 2, BF16><<<grid, 256, 0, st>>>(a); break;
-    case 3: tsmm_kernel<NKT, 3, BF16><<<grid, 256, 0, st>>>(a); break;
-    case 4: tsmm_kernel<NKT, 4, BF16><<<grid, 256, 0, st>>>(a); break;
-    case 5: tsmm_kernel<NKT, 5, BF16><<<grid, 256, 0, st>>>(a); break;
-    case 6: tsmm_kernel<NKT, 6, BF16><<<grid, 256, 0, st>>>(a); break;
-    case 7: tsmm_kernel<NKT, 7, BF16><<<grid, 256, 0, st>>>(a); break;
-    default: tsmm_kernel<NKT, 8, BF16><<<grid, 256, 0, st>>>(a); break;
+    case 1: tsmm_kernel<NKT, 1, BF16><<<grid, kTsmmThreads, 0, st>>>(a); break;
+    case 2: tsmm_kernel<NKT, 2, BF16><<<grid, kTsmmThreads, 0, st>>>(a); break;
+    case 3: tsmm_kernel<NKT, 3, BF16><<<grid, kTsmmThreads, 0, st>>>(a); break;
+    case 4: tsmm_kernel<NKT, 4, BF16><<<grid, kTsmmThreads, 0, st>>>(a); break;
+    case 5: tsmm_kernel<NKT, 5, BF16><<<grid, kTsmmThreads, 0, st>>>(a); break;
+    case 6: tsmm_kernel<NKT, 6, BF16><<<grid, kTsmmThreads, 0, st>>>(a); break;
+    case 7: tsmm_kernel<NKT, 7, BF16><<<grid, kTsmmThreads, 0, st>>>(a); break;
+    default: tsmm_kernel<NKT, 8, BF16><<<grid, kTsmmThreads, 0, st>>>(a); break;
   }
 }
 
 template <bool BF16>
 void tsmm_dispatch(int nkt, int nct, unsigned grid, const TsmmArgs& a, hipStream_t st) {
-  // k extents are rounded up to multiples of 32 (8 k-steps of 4)
+  // k extents are rounded up to multiples of 32 (8 k-steps of 4); vector loads need 16-byte
+  // (FP32) or 8-byte (BF16) aligned rows, which the dispatcher checks
   if (nkt <= 8) tsmm_dispatch_c<8, BF16>(nct, grid, a, st);
   else if (nkt <= 16) tsmm_dispatch_c<16, BF16>(nct, grid, a, st);
   else if (nkt <= 24) tsmm_dispatch_c<24, BF16>(nct, grid, a, st);
@@ -112,12 +165,14 @@ void tsmm_dispatch(int nkt, int nct, unsigned grid, const TsmmArgs& a, hipStream
 void launch_tsmm(const void* X, bool x_bf16, int ldx, int64_t rows, int kdim, const double* B, int ldb, int c,
                  int c_out, float* out, int ldo, uint16_t* out_bf16, int ldo16, bool accumulate, hipStream_t st) {
   if (rows <= 0 || c_out <= 0) return;
-  TsmmArgs a{X, ldx, rows, kdim, B, ldb, c, c_out, out, ldo, out_bf16, ldo16, accumulate ? 1 : 0};
+  const uintptr_t xa = reinterpret_cast<uintptr_t>(X);
+  const int vec = x_bf16 ? ((ldx % 4) == 0 && (xa % 8) == 0) : ((ldx % 4) == 0 && (xa % 16) == 0);
+  TsmmArgs a{X, ldx, rows, kdim, B, ldb, c, c_out, out, ldo, out_bf16, ldo16, accumulate ? 1 : 0, vec};
   const int nkt = (kdim + 3) / 4;
   const int nct = (c_out + 15) / 16;
   const int64_t ntiles = (rows + 15) / 16;
-  int64_t grid = (ntiles + 3) / 4;
-  if (grid > 2048) grid = 2048;
+  int64_t grid = (ntiles + kTsmmWaves - 1) / kTsmmWaves;
+  if (grid > 1024) grid = 1024;
   if (x_bf16) tsmm_dispatch<true>(nkt, nct, (unsigned)grid, a, st);
   else tsmm_dispatch<false>(nkt, nct, (unsigned)grid, a, st);
 }
