@@ -44,7 +44,9 @@ extern "C" {
 #define FRPCA_T_BWD 8     /* adjoint: cross-Gram, k x k terms, panels                  */
 #define FRPCA_T_SDDMM 9   /* adjoint projected onto the sparsity pattern              */
 #define FRPCA_T_SPMM_FIX 10 /* merge-path carry fix-up of both products               */
-#define FRPCA_NTIMERS 11
+#define FRPCA_T_SPMM_COMB 11 /* row-block partials of the transpose product combined   */
+#define FRPCA_T_SPMM_TAIL 12 /* transpose product, columns outside the row-block part  */
+#define FRPCA_NTIMERS 13
 
 typedef struct frpca_ctx* frpca_t;
 
@@ -70,6 +72,9 @@ typedef struct {
   int rank_dropped;       /* output singular values set to 0 by rank_tol (last run)   */
   size_t workspace_bytes; /* device memory currently held by the handle               */
   double create_ms;       /* wall time of frpca_create (validation + CSC mirror)       */
+  int64_t hot_cols;       /* columns whose A^T products run in row blocks (0: none)   */
+  int64_t row_blocks;     /* row blocks of 4096 rows used for them                    */
+  int64_t hot_nnz;        /* nonzeros in those columns                                */
   double t_ms[FRPCA_NTIMERS];   /* accumulated GPU time per kernel class (opts.timing) */
   int64_t t_count[FRPCA_NTIMERS]; /* number of timed launches per class                */
 } frpca_info;

@@ -92,6 +92,7 @@ class FrPCA:
             "m": inf.m, "n": inf.n, "nnz": inf.nnz, "orientation": inf.orientation, "k": inf.k,
             "s": inf.s, "passes": inf.passes, "rank_dropped": inf.rank_dropped,
             "workspace_bytes": inf.workspace_bytes, "create_ms": inf.create_ms,
+            "hot_cols": inf.hot_cols, "row_blocks": inf.row_blocks, "hot_nnz": inf.hot_nnz,
             "t_ms": {n: inf.t_ms[i] for i, n in enumerate(TIMER_NAMES)},
             "t_count": {n: inf.t_count[i] for i, n in enumerate(TIMER_NAMES)},
         }

@@ -17,9 +17,10 @@ FRPCA_EINVAL = -1
 FRPCA_ENOMEM = -2
 FRPCA_EHIP = -3
 FRPCA_ESTATE = -4
-NTIMERS = 11
+NTIMERS = 13
 TIMER_NAMES = ("gauss", "spmm_fwd", "spmm_back", "gram", "eig", "lu", "tsmm", "sign", "bwd", "sddmm",
-               "spmm_fixup")
+               "spmm_fixup", "spmm_combine",
+               "spmm_back_tail")
 
 
 class FrpcaError(RuntimeError):
@@ -36,7 +37,8 @@ class FrpcaOpts(ctypes.Structure):
 class FrpcaInfo(ctypes.Structure):
     _fields_ = [("m", c_int64), ("n", c_int64), ("nnz", c_int64), ("orientation", c_int),
                 ("k", c_int), ("s", c_int), ("passes", c_int), ("rank_dropped", c_int),
-                ("workspace_bytes", c_size_t), ("create_ms", c_double),
+                ("workspace_bytes", c_size_t), ("create_ms", c_double), ("hot_cols", c_int64),
+                ("row_blocks", c_int64), ("hot_nnz", c_int64),
                 ("t_ms", c_double * NTIMERS), ("t_count", c_int64 * NTIMERS)]
 
 

@@ -86,6 +86,13 @@ struct frpca_ctx {
   int32_t* perm = nullptr;
   float* val_csc = nullptr;
   MergePlan csr, csc;
+  // blocked column order for A^T Y with a long gathered panel (k_bcsc.hip); absent when no
+  // column is hot
+  bool has_bcsc = false;
+  MergePlan bhotp, btailp;  // hot segments (sweep mode) and tail columns
+  int32_t *bptr = nullptr, *bptr_tail = nullptr, *brow = nullptr, *bperm = nullptr, *colmap = nullptr;
+  float* bval = nullptr;
+  int64_t bhot = 0, bnblk = 0, bnseg = 0;
 
   // forward-run workspace
   void* ws = nullptr;
@@ -98,6 +105,7 @@ struct frpca_ctx {
   double *B1 = nullptr, *B2 = nullptr;
   int *order = nullptr, *ndrop = nullptr;
   double* eig_tmp = nullptr;
+  float* bpart = nullptr;  // partial rows of the blocked transpose product
   void *lu_tmp = nullptr, *sign_tmp = nullptr;
 
   // backward workspace
@@ -185,14 +193,16 @@ struct frpca_ctx {
     pending.clear();
   }
 
-  void build_plan(MergePlan& p, const int32_t* ptr, const int32_t* idx, const float* v, int64_t nseg) {
+  void build_plan(MergePlan& p, const int32_t* ptr, const int32_t* idx, const float* v, int64_t nseg,
+                  bool sweep = false, int64_t plan_nnz = -1) {
     p.ptr = ptr;
     p.idx = idx;
     p.val = v;
     p.nseg = nseg;
-    p.nnz = nnz;
-    p.ipw = merge_items_per_wave(nseg, nnz);
-    p.nwaves = std::max<int64_t>(1, (nseg + nnz + p.ipw - 1) / p.ipw);
+    p.nnz = plan_nnz >= 0 ? plan_nnz : nnz;
+    p.sweep = sweep ? 1 : 0;
+    p.ipw = sweep ? kSweepItemsPerWave : merge_items_per_wave(nseg, p.nnz);
+    p.nwaves = std::max<int64_t>(1, (nseg + p.nnz + p.ipw - 1) / p.ipw);
     p.part_seg = static_cast<int32_t*>(alloc_owned((p.nwaves + 1) * sizeof(int32_t)));
     p.part_e = static_cast<int32_t*>(alloc_owned((p.nwaves + 1) * sizeof(int32_t)));
     p.fix_w0 = static_cast<int32_t*>(alloc_owned(p.nwaves * sizeof(int32_t)));
@@ -200,6 +210,15 @@ struct frpca_ctx {
     p.head = static_cast<float*>(alloc_owned(p.nwaves * 128 * sizeof(float)));
     launch_merge_partition(p, stream);
     launch_merge_fixplan(p, stream);
+  }
+
+  // A^T in through the blocked order: merge-path into the partial rows, carry fix-up, then
+  // the fixed-order combine into out (n x ld_out)
+  void bcsc_product(int lp, const void* in, bool in_bf16, int ld_in, float* part, float* out32, uint16_t* out16,
+                    int ld_out, hipStream_t st) {
+    launch_spmm(bhotp, lp, in, in_bf16, ld_in, part, nullptr, lp, st);
+    launch_spmm(btailp, lp, in, in_bf16, ld_in, part + (size_t)bhotp.nseg * lp, nullptr, lp, st);
+    launch_bcsc_combine(part, lp, colmap, n, bhot, bnblk, lp, out32, out16, ld_out, st);
   }
 
   int64_t short_rows() const { return std::min(m, n); }
@@ -232,6 +251,7 @@ struct frpca_ctx {
       ndrop = a.take<int>(4);
       lu_tmp = a.take<char>(lu_temp_bytes(Ns, lp));
       sign_tmp = a.take<char>(sign_partial_bytes(Nl, kMaxL));
+      bpart = has_bcsc ? a.take<float>((size_t)bnseg * lp) : nullptr;
     };
     Arena probe;
     plan(probe);
@@ -350,12 +370,60 @@ int frpca_create(frpca_t* out, int64_t m, int64_t n, int64_t nnz, const int64_t*
       h->build_plan(h->csr, h->rp32, col, val, m);
       h->build_plan(h->csc, h->cp32, h->row_csc, h->val_csc, n);
       check_launch();
+      // blocked column order for the transpose product (hot columns split by row block)
+      if (nnz > 0) {
+        const int64_t nblk = (m + (1 << kBcscRowShift) - 1) >> kBcscRowShift;
+        const int32_t thresh = (int32_t)std::min<int64_t>(INT32_MAX, (int64_t)kHotPerBlock * nblk);
+        DeviceTemp hot((n + 1) * sizeof(int32_t)), tail((n + 1) * sizeof(int32_t));
+        DeviceTemp hpre((n + 1) * sizeof(int32_t)), tpre((n + 1) * sizeof(int32_t)), stmp(scan_temp_bytes(n));
+        launch_hot_flags(h->cp32, n, thresh, static_cast<int32_t*>(hot.p), static_cast<int32_t*>(tail.p), st);
+        exclusive_scan_i32(static_cast<int32_t*>(hot.p), static_cast<int32_t*>(hpre.p), n, stmp.p, st);
+        exclusive_scan_i32(static_cast<int32_t*>(tail.p), static_cast<int32_t*>(tpre.p), n, stmp.p, st);
+        int32_t hh = 0;
+        FRPCA_HIP(hipMemcpyAsync(&hh, static_cast<int32_t*>(hpre.p) + n, sizeof(int32_t), hipMemcpyDeviceToHost,
+                                 st));
+        FRPCA_HIP(hipStreamSynchronize(st));
+        const int64_t nhs = nblk * (int64_t)hh, nseg = nhs + (n - hh);
+        if (hh > 0 && nseg < INT32_MAX) {
+          h->has_bcsc = true;
+          h->bhot = hh;
+          h->bnblk = nblk;
+          h->bnseg = nseg;
+          h->colmap = static_cast<int32_t*>(h->alloc_owned(n * sizeof(int32_t)));
+          h->bptr = static_cast<int32_t*>(h->alloc_owned((nseg + 1) * sizeof(int32_t)));
+          h->brow = static_cast<int32_t*>(h->alloc_owned(nnz * sizeof(int32_t)));
+          h->bperm = static_cast<int32_t*>(h->alloc_owned(nnz * sizeof(int32_t)));
+          h->bval = static_cast<float*>(h->alloc_owned(nnz * sizeof(float)));
+          launch_colmap(static_cast<int32_t*>(hot.p), static_cast<int32_t*>(hpre.p), static_cast<int32_t*>(tpre.p),
+                        n, h->colmap, st);
+          uint32_t* bv = reinterpret_cast<uint32_t*>(h->bperm);
+          launch_bcsc_keys(static_cast<int32_t*>(row_of.p), col, nnz, h->colmap, hh, nblk, kk, st);
+          iota_kernel<<<(unsigned)((nnz + 255) / 256), 256, 0, st>>>(bv, nnz);
+          radix_sort_pairs(kk, bv, static_cast<uint32_t*>(keys_alt.p), static_cast<uint32_t*>(vals_alt.p), nnz,
+                           bits_for(nseg - 1), rtmp.p, st);
+          launch_ptr_from_sorted(kk, nnz, nseg, h->bptr, st);
+          launch_gather_csc(bv, static_cast<int32_t*>(row_of.p), val, nnz, h->brow, h->bval, st);
+          check_launch();
+          int32_t nnz_hot = 0;
+          FRPCA_HIP(hipMemcpyAsync(&nnz_hot, h->bptr + nhs, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+          FRPCA_HIP(hipStreamSynchronize(st));
+          h->bptr_tail = static_cast<int32_t*>(h->alloc_owned((n - hh + 1) * sizeof(int32_t)));
+          launch_rebase(h->bptr + nhs, n - hh + 1, nnz_hot, h->bptr_tail, st);
+          h->build_plan(h->bhotp, h->bptr, h->brow, h->bval, nhs, true, nnz_hot);
+          h->build_plan(h->btailp, h->bptr_tail, h->brow + nnz_hot, h->bval + nnz_hot, n - hh, false,
+                        nnz - nnz_hot);
+          check_launch();
+        }
+      }
       FRPCA_HIP(hipStreamSynchronize(st));
     }
     h->info.m = m;
     h->info.n = n;
     h->info.nnz = nnz;
     h->info.orientation = m >= n ? 6 : 5;
+    h->info.hot_cols = h->bhot;
+    h->info.row_blocks = h->has_bcsc ? h->bnblk : 0;
+    h->info.hot_nnz = h->has_bcsc ? h->bhotp.nnz : 0;
     h->info.create_ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   });
@@ -374,6 +442,7 @@ int frpca_set_values(frpca_t h, const float* val) {
     h->val = val;
     h->csr.val = val;
     launch_gather_values(h->perm, val, h->nnz, h->val_csc, h->stream);
+    if (h->has_bcsc) launch_gather_values(h->bperm, val, h->nnz, h->bval, h->stream);
     check_launch();
   });
 }
@@ -418,8 +487,15 @@ int frpca_run(frpca_t h, int k, int p_passes, int s_oversample, uint64_t seed, f
       else spmm(Fp, fwd_cls, h->Q, false, h->Y, nullptr);
     };
     auto back = [&] {
-      if (bf) spmm(Bp, back_cls, h->Yb, true, h->X, nullptr);
-      else spmm(Bp, back_cls, h->Y, false, h->X, nullptr);
+      const void* in = bf ? static_cast<const void*>(h->Yb) : static_cast<const void*>(h->Y);
+      if (a6 && h->has_bcsc) {
+        spmm(h->bhotp, back_cls, in, bf != 0, h->bpart, nullptr);
+        spmm(h->btailp, FRPCA_T_SPMM_TAIL, in, bf != 0, h->bpart + (size_t)h->bhotp.nseg * LP, nullptr);
+        frpca_ctx::Scope t(h, FRPCA_T_SPMM_COMB);
+        launch_bcsc_combine(h->bpart, LP, h->colmap, n, h->bhot, h->bnblk, LP, h->X, nullptr, LP, st);
+      } else {
+        spmm(Bp, back_cls, in, bf != 0, h->X, nullptr);
+      }
     };
     auto basis_from_B1 = [&] {
       frpca_ctx::Scope t(h, FRPCA_T_TSMM);
@@ -617,9 +693,17 @@ int frpca_spmm(frpca_t h, int trans, int l, const void* in, int in_bf16, int ld_
     FRPCA_CHECK(l >= 1 && l <= kMaxL && lp >= l, FRPCA_EINVAL,
                 "need 1 <= l <= 128 and leading dimensions >= l (rounded up to even)");
     FRPCA_CHECK(in && out, FRPCA_EINVAL, "NULL panel");
+    float* o32 = out_bf16 ? nullptr : static_cast<float*>(out);
+    uint16_t* o16 = out_bf16 ? static_cast<uint16_t*>(out) : nullptr;
+    if (trans && h->has_bcsc) {
+      DeviceTemp part((size_t)h->bnseg * lp * sizeof(float));
+      h->bcsc_product(lp, in, in_bf16 != 0, ld_in, static_cast<float*>(part.p), o32, o16, ld_out, h->stream);
+      check_launch();
+      FRPCA_HIP(hipStreamSynchronize(h->stream));
+      return;
+    }
     const MergePlan& p = trans ? h->csc : h->csr;
-    launch_spmm(p, lp, in, in_bf16 != 0, ld_in, out_bf16 ? nullptr : static_cast<float*>(out),
-                out_bf16 ? static_cast<uint16_t*>(out) : nullptr, ld_out, h->stream);
+    launch_spmm(p, lp, in, in_bf16 != 0, ld_in, o32, o16, ld_out, h->stream);
     check_launch();
     FRPCA_HIP(hipStreamSynchronize(h->stream));
   });

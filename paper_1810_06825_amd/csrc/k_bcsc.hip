@@ -1,0 +1,108 @@
+// Blocked column-major order for the transpose product A^T Y when the gathered panel Y is
+// too large for the caches (Alg. 6: Y is m x l with m >> n).
+//
+// In plain column order, each nonzero of A^T Y gathers a whole row of Y and the ~nnz/m
+// nonzeros that share a row of Y are far apart in time, so every gather misses the caches.
+// Frequent ("hot") columns are therefore split by row block: their nonzeros are ordered by
+// (row block, hot column, row), so all hot columns sweep one block of Y rows (4096 rows,
+// 2 MB at l = 128) while it sits in L2, each (row block, hot column) pair being one merge-path
+// segment whose sum is a partial row. The remaining ("tail") columns keep one segment each.
+// A combine kernel adds the partials of each hot column over the row blocks in a fixed order
+// and copies the tail rows, so the product stays deterministic.
+//
+// A column is hot when it holds at least kHotPerBlock nonzeros per row block on average, so
+// every partial row amortizes its write over that many gathers. Segment order: the nblk x H
+// hot segments (row block major), then one segment per tail column. The two parts run as
+// separate merge-path launches: the hot one sweeps the row blocks in narrow rounds (each XCD
+// on its own stretch) so its gathers hit L2, and the tail's random-row gathers, which would
+// evict those blocks, come afterwards.
+#include "kernels.h"
+
+namespace frpca {
+namespace {
+
+__global__ void hot_flags_kernel(const int32_t* cp, int64_t n, int32_t thresh, int32_t* hot, int32_t* tail) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int32_t h = (cp[i + 1] - cp[i]) >= thresh ? 1 : 0;
+  hot[i] = h;
+  tail[i] = 1 - h;
+}
+
+__global__ void colmap_kernel(const int32_t* hot, const int32_t* hpre, const int32_t* tpre, int64_t n,
+                              int32_t* colmap) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  colmap[i] = hot[i] ? hpre[i] : -1 - tpre[i];
+}
+
+__global__ void keys_kernel(const int32_t* row_of, const int32_t* col, int64_t nnz, const int32_t* colmap,
+                            int64_t hot_cols, int64_t nblk, uint32_t* keys) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= nnz) return;
+  const int32_t cm = colmap[col[e]];
+  keys[e] = cm >= 0 ? (uint32_t)((int64_t)(row_of[e] >> kBcscRowShift) * hot_cols + cm)
+                    : (uint32_t)(nblk * hot_cols + (-1 - cm));
+}
+
+// Segment pointers of the tail part, rebased to its first nonzero.
+__global__ void rebase_kernel(const int32_t* ptr, int64_t count, int32_t base, int32_t* out) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < count) out[i] = ptr[i] - base;
+}
+
+// One wave per output row c; a lane owns columns 2 lane and 2 lane + 1.
+__global__ __launch_bounds__(256) void combine_kernel(const float* P, int ldp, const int32_t* colmap, int64_t n,
+                                                      int64_t hot_cols, int64_t nblk, int lp, float* X32,
+                                                      uint16_t* X16, int ldx) {
+  const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int col = 2 * (threadIdx.x & 63);
+  if (c >= n || col >= lp) return;
+  const int32_t cm = colmap[c];
+  float2 s;
+  if (cm >= 0) {
+    s = make_float2(0.f, 0.f);
+    for (int64_t b = 0; b < nblk; ++b) {
+      const float2 v = *reinterpret_cast<const float2*>(P + (size_t)(b * hot_cols + cm) * ldp + col);
+      s.x += v.x;
+      s.y += v.y;
+    }
+  } else {
+    s = *reinterpret_cast<const float2*>(P + (size_t)(nblk * hot_cols + (-1 - cm)) * ldp + col);
+  }
+  const size_t o = (size_t)c * ldx + col;
+  if (X32) store2_f32(X32, o, s);
+  if (X16) store2_bf16(X16, o, s);
+}
+
+}  // namespace
+
+void launch_hot_flags(const int32_t* cp, int64_t n, int32_t thresh, int32_t* hot, int32_t* tail, hipStream_t st) {
+  if (n <= 0) return;
+  hot_flags_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(cp, n, thresh, hot, tail);
+}
+
+void launch_colmap(const int32_t* hot, const int32_t* hpre, const int32_t* tpre, int64_t n, int32_t* colmap,
+                   hipStream_t st) {
+  if (n <= 0) return;
+  colmap_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(hot, hpre, tpre, n, colmap);
+}
+
+void launch_bcsc_keys(const int32_t* row_of, const int32_t* col, int64_t nnz, const int32_t* colmap,
+                      int64_t hot_cols, int64_t nblk, uint32_t* keys, hipStream_t st) {
+  if (nnz <= 0) return;
+  keys_kernel<<<(unsigned)((nnz + 255) / 256), 256, 0, st>>>(row_of, col, nnz, colmap, hot_cols, nblk, keys);
+}
+
+void launch_rebase(const int32_t* ptr, int64_t count, int32_t base, int32_t* out, hipStream_t st) {
+  if (count <= 0) return;
+  rebase_kernel<<<(unsigned)((count + 255) / 256), 256, 0, st>>>(ptr, count, base, out);
+}
+
+void launch_bcsc_combine(const float* P, int ldp, const int32_t* colmap, int64_t n, int64_t hot_cols, int64_t nblk,
+                         int lp, float* X32, uint16_t* X16, int ldx, hipStream_t st) {
+  if (n <= 0) return;
+  combine_kernel<<<(unsigned)((n + 3) / 4), 256, 0, st>>>(P, ldp, colmap, n, hot_cols, nblk, lp, X32, X16, ldx);
+}
+
+}  // namespace frpca

@@ -31,9 +31,25 @@ struct SpmmArgs {
   int lp;  // columns computed (even, <= 128)
   float* carry;
   float* head;
+  int sweep;
 };
 
+// Sweep mode: a grid of resident waves walks the partitions in rounds (round i covers
+// partitions [i G, (i+1) G) for G resident waves), and within a round the blocks that the
+// hardware places on one XCD (round-robin by block index) take one contiguous stretch. The
+// partitions in flight then cover a narrow band of the segment order, which the row-blocked
+// transpose product needs for its gathered panel rows to stay in each XCD's L2.
+#ifndef FRPCA_SWEEP_XCD
+#define FRPCA_SWEEP_XCD 1
+#endif
+__device__ __forceinline__ int64_t sweep_block(int64_t round) {
+  const int64_t g = gridDim.x, q = g / 8, r = g % 8, b = blockIdx.x, x = b % 8;
+  if (!FRPCA_SWEEP_XCD) return round * g + b;
+  return round * g + x * q + min(x, r) + b / 8;
+}
+
 constexpr int kBatch = 8;  // gathers in flight per wave
+constexpr unsigned kSweepBlocks = 2048;  // resident blocks of 4 waves in sweep mode (8 per CU)
 
 // The sparse operand is read exactly once per product: non-temporal loads keep it from
 // displacing the gathered panel rows in the caches.
@@ -43,11 +59,7 @@ __device__ __forceinline__ T stream_load(const T* p) {
 }
 
 template <bool IN_BF16>
-__global__ __launch_bounds__(256) void spmm_merge_kernel(SpmmArgs a) {
-  const int lane = threadIdx.x & 63;
-  // wave index made explicitly uniform so the partition bounds are scalar values
-  const int64_t w = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (w >= a.nwaves) return;
+__device__ __forceinline__ void spmm_partition(const SpmmArgs& a, int64_t w, int lane) {
   const int col = 2 * lane;
   const bool act = col < a.lp;
   int seg = a.part_seg[w];
@@ -77,7 +89,10 @@ __global__ __launch_bounds__(256) void spmm_merge_kernel(SpmmArgs a) {
 
   // The (index, value) stream is read 64 entries at a time with one coalesced (streaming)
   // load per wave; entries are broadcast with readlane, the next window is in flight while
-  // the current one is consumed.
+  // the current one is consumed. Gathers run as a two-stage pipeline: batch j+1's panel rows
+  // are requested before batch j's are accumulated, so up to 2 kBatch rows are in flight per
+  // wave. Lanes past lp gather column 0 (in bounds, never stored) instead of branching.
+  const int gcol = act ? col : 0;
   int wbase = e;
   int widx = 0, nidx = 0;
   float wval = 0.f, nval = 0.f;
@@ -85,6 +100,19 @@ __global__ __launch_bounds__(256) void spmm_merge_kernel(SpmmArgs a) {
     widx = stream_load(a.idx + wbase + lane);
     wval = stream_load(a.val + wbase + lane);
   }
+  float pv[kBatch];
+  float2 px[kBatch];
+  int pe = 0, pnb = 0;  // pending batch: first entry and size (0: none)
+  auto consume = [&]() {
+#pragma unroll
+    for (int t = 0; t < kBatch; ++t) {
+      if (t < pnb) {
+        while (next_end <= pe + t) emit();
+        acc.x = fmaf(pv[t], px[t].x, acc.x);
+        acc.y = fmaf(pv[t], px[t].y, acc.y);
+      }
+    }
+  };
   while (e < e_stop) {
     const int wend = min(wbase + 64, e_stop);
     if (wbase + 64 + lane < e_stop) {
@@ -94,37 +122,218 @@ __global__ __launch_bounds__(256) void spmm_merge_kernel(SpmmArgs a) {
     while (e < wend) {
       const int nb = min(kBatch, wend - e);
       const int off = e - wbase;
-      int c[kBatch];
       float v[kBatch];
       float2 x[kBatch];
+      if (nb == kBatch) {
 #pragma unroll
-      for (int t = 0; t < kBatch; ++t) {
-        if (t < nb) {
-          c[t] = __builtin_amdgcn_readlane(widx, off + t);
+        for (int t = 0; t < kBatch; ++t) {
+          const int c = __builtin_amdgcn_readlane(widx, off + t);
           v[t] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wval), off + t));
+          x[t] = load2<IN_BF16>(a.in, (size_t)c * a.ld_in + gcol);
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < kBatch; ++t) {
+          v[t] = 0.f;
+          x[t] = make_float2(0.f, 0.f);
+          if (t < nb) {
+            const int c = __builtin_amdgcn_readlane(widx, off + t);
+            v[t] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wval), off + t));
+            x[t] = load2<IN_BF16>(a.in, (size_t)c * a.ld_in + gcol);
+          }
         }
       }
+      consume();
 #pragma unroll
       for (int t = 0; t < kBatch; ++t) {
-        x[t] = make_float2(0.f, 0.f);
-        if (t < nb && act) x[t] = load2<IN_BF16>(a.in, (size_t)c[t] * a.ld_in + col);
+        pv[t] = v[t];
+        px[t] = x[t];
       }
-#pragma unroll
-      for (int t = 0; t < kBatch; ++t) {
-        if (t < nb) {
-          while (next_end <= e + t) emit();
-          acc.x = fmaf(v[t], x[t].x, acc.x);
-          acc.y = fmaf(v[t], x[t].y, acc.y);
-        }
-      }
+      pe = e;
+      pnb = nb;
       e += nb;
     }
     wbase += 64;
     widx = nidx;
     wval = nval;
   }
+  consume();
   while (seg < seg_stop) emit();
   if (seg_stop < a.nseg && act) store2_f32(a.carry, (size_t)w * 128 + col, acc);
+}
+
+template <bool IN_BF16>
+__global__ __launch_bounds__(256) void spmm_merge_kernel(SpmmArgs a) {
+  const int lane = threadIdx.x & 63;
+  // wave index made explicitly uniform so the partition bounds are scalar values
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (!a.sweep) {
+    const int64_t w = (int64_t)blockIdx.x * 4 + wv;
+    if (w < a.nwaves) spmm_partition<IN_BF16>(a, w, lane);
+    return;
+  }
+  for (int64_t round = 0;; ++round) {
+    const int64_t w = sweep_block(round) * 4 + wv;
+    if (w >= a.nwaves) break;
+    spmm_partition<IN_BF16>(a, w, lane);
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Paired gathers (panels of 4-aligned width): vector-memory instructions, not bytes, bound
+// the products above (each one costs the texture addresser the same cycles whatever its
+// width), so a 16-byte load per lane lets one instruction fetch two panel rows: lanes 0-31
+// take the even entry of each pair of nonzeros, lanes 32-63 the odd one, a lane covering four
+// columns. The halves accumulate separately and are added with a cross-half shuffle when a
+// segment ends; a segment ending between the two entries of a pair is handled by letting
+// only the even half accumulate, emitting, then adding the odd half.
+#ifndef FRPCA_SPMM_PAIRS
+#define FRPCA_SPMM_PAIRS 4
+#endif
+constexpr int kPairs = FRPCA_SPMM_PAIRS;  // pairs per batch; two batches in flight
+
+template <bool IN_BF16>
+__device__ __forceinline__ float4 load4(const void* base, size_t idx) {
+  if constexpr (IN_BF16) {
+    const uint2 w = *reinterpret_cast<const uint2*>(static_cast<const uint16_t*>(base) + idx);
+    return make_float4(__uint_as_float(w.x << 16), __uint_as_float(w.x & 0xFFFF0000u), __uint_as_float(w.y << 16),
+                       __uint_as_float(w.y & 0xFFFF0000u));
+  } else {
+    return *reinterpret_cast<const float4*>(static_cast<const float*>(base) + idx);
+  }
+}
+
+__device__ __forceinline__ void fma4(float4& acc, float v, const float4& x) {
+  acc.x = fmaf(v, x.x, acc.x);
+  acc.y = fmaf(v, x.y, acc.y);
+  acc.z = fmaf(v, x.z, acc.z);
+  acc.w = fmaf(v, x.w, acc.w);
+}
+
+template <bool IN_BF16>
+__device__ __forceinline__ void spmm_partition4(const SpmmArgs& a, int64_t w, int lane) {
+  const int half = lane >> 5;
+  const int col = 4 * (lane & 31);
+  const bool act = col < a.lp;
+  const int gcol = act ? col : 0;
+  int seg = a.part_seg[w];
+  const int seg_stop = a.part_seg[w + 1];
+  int e = a.part_e[w];
+  const int e_stop = a.part_e[w + 1];
+  bool pending_head = (seg < a.nseg) && (a.ptr[seg] < e);
+  int next_end = (seg < seg_stop) ? a.ptr[seg + 1] : INT_MAX;
+  float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+
+  auto emit = [&]() {
+    float4 t;
+    t.x = acc.x + __shfl_xor(acc.x, 32);
+    t.y = acc.y + __shfl_xor(acc.y, 32);
+    t.z = acc.z + __shfl_xor(acc.z, 32);
+    t.w = acc.w + __shfl_xor(acc.w, 32);
+    if (half == 0 && act) {
+      if (pending_head) {
+        *reinterpret_cast<float4*>(a.head + (size_t)w * 128 + col) = t;
+      } else {
+        const size_t o = (size_t)seg * a.ld_out + col;
+        if (a.out_f32) *reinterpret_cast<float4*>(a.out_f32 + o) = t;
+        if (a.out_bf16) {
+          uint2 b;
+          b.x = (uint32_t)f32_to_bf16(t.x) | ((uint32_t)f32_to_bf16(t.y) << 16);
+          b.y = (uint32_t)f32_to_bf16(t.z) | ((uint32_t)f32_to_bf16(t.w) << 16);
+          *reinterpret_cast<uint2*>(a.out_bf16 + o) = b;
+        }
+      }
+    }
+    pending_head = false;
+    acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    ++seg;
+    next_end = (seg < seg_stop) ? a.ptr[seg + 1] : INT_MAX;
+  };
+
+  int wbase = e;
+  int widx = 0, nidx = 0;
+  float wval = 0.f, nval = 0.f;
+  if (wbase + lane < e_stop) {
+    widx = stream_load(a.idx + wbase + lane);
+    wval = stream_load(a.val + wbase + lane);
+  }
+  float pv[kPairs];
+  float4 px[kPairs];
+  int pe = 0, pend = 0;  // pending batch: entries [pe, pend)
+  auto consume = [&]() {
+#pragma unroll
+    for (int p = 0; p < kPairs; ++p) {
+      const int ep = pe + 2 * p;
+      if (ep < pend) {
+        while (next_end <= ep) emit();
+        if (ep + 1 < pend && next_end == ep + 1) {
+          fma4(acc, half == 0 ? pv[p] : 0.f, px[p]);
+          while (next_end <= ep + 1) emit();
+          fma4(acc, half == 1 ? pv[p] : 0.f, px[p]);
+        } else {
+          fma4(acc, pv[p], px[p]);
+        }
+      }
+    }
+  };
+  while (e < e_stop) {
+    const int wend = min(wbase + 64, e_stop);
+    if (wbase + 64 + lane < e_stop) {
+      nidx = stream_load(a.idx + wbase + 64 + lane);
+      nval = stream_load(a.val + wbase + 64 + lane);
+    }
+    while (e < wend) {
+      const int stop = min(e + 2 * kPairs, wend);
+      const int off = e - wbase;
+      float v[kPairs];
+      float4 x[kPairs];
+#pragma unroll
+      for (int p = 0; p < kPairs; ++p) {
+        // this half's entry of pair p (entries past the batch gather row 0 with weight 0)
+        const int src = off + 2 * p + half;
+        const bool valid = e + 2 * p + half < stop;
+        const int c = __shfl(widx, src & 63);
+        const float vv = __shfl(wval, src & 63);
+        v[p] = valid ? vv : 0.f;
+        x[p] = load4<IN_BF16>(a.in, (size_t)(valid ? c : 0) * a.ld_in + gcol);
+      }
+      consume();
+#pragma unroll
+      for (int p = 0; p < kPairs; ++p) {
+        pv[p] = v[p];
+        px[p] = x[p];
+      }
+      pe = e;
+      pend = stop;
+      e = stop;
+    }
+    wbase += 64;
+    widx = nidx;
+    wval = nval;
+  }
+  consume();
+  while (seg < seg_stop) emit();
+  if (seg_stop < a.nseg) {
+    const float4 t = make_float4(acc.x + __shfl_xor(acc.x, 32), acc.y + __shfl_xor(acc.y, 32),
+                                 acc.z + __shfl_xor(acc.z, 32), acc.w + __shfl_xor(acc.w, 32));
+    if (half == 0 && act) *reinterpret_cast<float4*>(a.carry + (size_t)w * 128 + col) = t;
+  }
+}
+
+template <bool IN_BF16>
+__global__ __launch_bounds__(256) void spmm_merge4_kernel(SpmmArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (!a.sweep) {
+    const int64_t w = (int64_t)blockIdx.x * 4 + wv;
+    if (w < a.nwaves) spmm_partition4<IN_BF16>(a, w, lane);
+    return;
+  }
+  for (int64_t round = 0;; ++round) {
+    const int64_t w = sweep_block(round) * 4 + wv;
+    if (w >= a.nwaves) break;
+    spmm_partition4<IN_BF16>(a, w, lane);
+  }
 }
 
 // out[c] = carry[w0] + ... + carry[w1-1] + head[w1] for segments cut by partition bounds.
@@ -159,8 +368,20 @@ void launch_spmm_main(const MergePlan& p, int lp, const void* in, bool in_bf16, 
                       uint16_t* out_bf16, int ld_out, hipStream_t st) {
   if (p.nwaves <= 0) return;
   SpmmArgs a{p.ptr, p.idx, p.val, p.part_seg, p.part_e, p.nseg, p.nwaves, in, ld_in, out_f32, out_bf16,
-             ld_out, lp, p.carry, p.head};
-  const unsigned grid = (unsigned)((p.nwaves + 3) / 4);
+             ld_out, lp, p.carry, p.head, p.sweep};
+  unsigned grid = (unsigned)((p.nwaves + 3) / 4);
+  if (p.sweep && grid > kSweepBlocks) grid = kSweepBlocks;
+  // paired 16-byte gathers when every row of in and out starts 16-byte (FP32) or 8-byte
+  // (BF16) aligned and the computed width is a multiple of 4
+  const size_t ein = in_bf16 ? 2 : 4;
+  const bool al_in = (reinterpret_cast<uintptr_t>(in) % (4 * ein)) == 0 && (ld_in % 4) == 0;
+  const bool al_out = (!out_f32 || (reinterpret_cast<uintptr_t>(out_f32) % 16) == 0) &&
+                      (!out_bf16 || (reinterpret_cast<uintptr_t>(out_bf16) % 8) == 0) && (ld_out % 4) == 0;
+  if ((lp % 4) == 0 && al_in && al_out) {
+    if (in_bf16) spmm_merge4_kernel<true><<<grid, 256, 0, st>>>(a);
+    else spmm_merge4_kernel<false><<<grid, 256, 0, st>>>(a);
+    return;
+  }
   if (in_bf16) spmm_merge_kernel<true><<<grid, 256, 0, st>>>(a);
   else spmm_merge_kernel<false><<<grid, 256, 0, st>>>(a);
 }

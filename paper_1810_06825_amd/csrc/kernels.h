@@ -35,6 +35,24 @@ void launch_gather_csc(const uint32_t* perm, const int32_t* row_of, const float*
 void launch_gather_values(const int32_t* perm, const float* val, int64_t nnz, float* out,
                           hipStream_t st);
 
+// ---------------------------------------------------------------- blocked column order
+// (hot columns split by blocks of 2^kBcscRowShift rows; see k_bcsc.hip)
+constexpr int kBcscRowShift = 12;
+#ifndef FRPCA_HOT_PER_BLOCK
+#define FRPCA_HOT_PER_BLOCK 12
+#endif
+constexpr int kHotPerBlock = FRPCA_HOT_PER_BLOCK;
+void launch_hot_flags(const int32_t* cp, int64_t n, int32_t thresh, int32_t* hot, int32_t* tail, hipStream_t st);
+void launch_colmap(const int32_t* hot, const int32_t* hpre, const int32_t* tpre, int64_t n, int32_t* colmap,
+                   hipStream_t st);
+// segments: nblk * hot_cols hot ones (row block major), then one per tail column
+void launch_bcsc_keys(const int32_t* row_of, const int32_t* col, int64_t nnz, const int32_t* colmap,
+                      int64_t hot_cols, int64_t nblk, uint32_t* keys, hipStream_t st);
+void launch_rebase(const int32_t* ptr, int64_t count, int32_t base, int32_t* out, hipStream_t st);
+// X[c] = sum over row blocks of the hot partial rows of c (fixed order), or the tail row of c.
+void launch_bcsc_combine(const float* P, int ldp, const int32_t* colmap, int64_t n, int64_t hot_cols, int64_t nblk,
+                         int lp, float* X32, uint16_t* X16, int ldx, hipStream_t st);
+
 // ---------------------------------------------------------------- merge-path products
 struct MergePlan {
   const int32_t* ptr = nullptr;   // segment pointers [nseg+1]
@@ -47,10 +65,15 @@ struct MergePlan {
   int32_t* part_e = nullptr;      // [nwaves+1] first nonzero of each partition
   int32_t* fix_w0 = nullptr;      // [nwaves] first carrying wave of the segment whose
                                   //   head ends in wave w, or -1
+  int sweep = 0;                  // resident waves walk the partitions in narrow rounds
   float* carry = nullptr;         // [nwaves*128] partial sums carried out of each wave
   float* head = nullptr;          // [nwaves*128] partial sums of continued first segments
 };
 int64_t merge_items_per_wave(int64_t nseg, int64_t nnz);
+#ifndef FRPCA_SWEEP_IPW
+#define FRPCA_SWEEP_IPW 256
+#endif
+constexpr int64_t kSweepItemsPerWave = FRPCA_SWEEP_IPW;  // partition size of sweep-mode plans
 void launch_merge_partition(MergePlan& p, hipStream_t st);
 void launch_merge_fixplan(MergePlan& p, hipStream_t st);
 // out[seg, 0:lp) = sum_{e in seg} val[e] * in[idx[e], 0:lp)  (lp even, <= 128):
