@@ -205,6 +205,7 @@ def main():
         for _ in range(2):
             mat.backward(U, S, V, dU, dS, None)
         torch.cuda.synchronize()
+        mat.reset_timers()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         nb = max(3, args.steps // 2)
@@ -213,6 +214,9 @@ def main():
         e1.record()
         torch.cuda.synchronize()
         bms = e0.elapsed_time(e1) / nb
+        binf = mat.info()
+        extras["backward_per_class_ms"] = {kk: round(binf["t_ms"][kk] / nb, 4) for kk in binf["t_ms"]
+                                           if binf["t_count"][kk]}
         extras["ms_backward"] = round(bms, 3)
         extras["fwd_bwd_over_fwd"] = round((ms + bms) / ms, 3)
         log(f"backward {bms:.3f} ms, (fwd+bwd)/fwd = {(ms + bms) / ms:.3f}")

@@ -22,7 +22,7 @@
 //     r where |gamma_r| = |s_r + p_r + mu| is smallest (stationary and progressive qd
 //     transforms): z_r = 1, z_i = -L+_i z_i+1 above r, z_i+1 = -U-_i z_i below r. Eigenvalues
 //     with a relative gap under 1e-3 form clusters; their vectors start from the twisted
-//     ones (slightly perturbed) and take four steps of inverse iteration with shifts kept
+//     ones (slightly perturbed) and take three steps of inverse iteration with shifts kept
 //     10 eps apart, each followed by Gram-Schmidt (twice) against the earlier members.
 //  5. W = H_0 H_1 ... H_{n-3} Z, eigenvalues sorted ascending (the order Alg. 2 and the final
 //     selection ind = k+s:-1:s+1 rely on; ties in index order).
@@ -35,7 +35,8 @@ constexpr int kT = 1024;             // threads
 constexpr int kS = kMaxL + 1;        // odd LDS row stride (doubles)
 constexpr double kEps = 2.220446049250313e-16;
 constexpr double kMinRelGap = 1e-3;  // relative gap below which eigenvalues form a cluster
-constexpr int kClusterIters = 4;
+constexpr int kClusterIters = 3;
+constexpr int kLdsSlots = 10;        // clustered columns whose L+ factors stay in LDS
 
 __device__ __forceinline__ double wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
@@ -165,7 +166,8 @@ __global__ __launch_bounds__(kT) void syev_kernel(const double* G, int ldg, int 
   __shared__ double red[kT / 64], red2[kT / 64];
   __shared__ double colbuf[kMaxL];
   __shared__ int bstart[kMaxL], bsize[kMaxL], bbad[kMaxL], cl0[kMaxL], incl[kMaxL], rank_s[kMaxL];
-  __shared__ int gs_list[kMaxL];
+  __shared__ int gs_list[kMaxL], slot_s[kMaxL];
+  __shared__ double lds_lp[kLdsSlots * kMaxL];
   __shared__ int sh_int[4];
   __shared__ double sh_dbl[4];
   double* house = scratch;                   // kMaxL x kMaxL reflectors
@@ -200,47 +202,48 @@ __global__ __launch_bounds__(kT) void syev_kernel(const double* G, int ldg, int 
   }
   __syncthreads();
   for (int k = 0; k + 2 < n; ++k) {
-    double sigma = 0.0;
-#pragma unroll
-    for (int w = 0; w < kT / 64; ++w) sigma += red[w];
-    const double x0 = colbuf[k + 1];
-    double tk = 0.0, beta = x0, scal = 0.0;
-    if (sigma != 0.0) {
-      const double mu0 = sqrt(x0 * x0 + sigma);
-      beta = (x0 <= 0.0) ? mu0 : -mu0;
-      tk = (beta - x0) / beta;
-      scal = 1.0 / (x0 - beta);
-    }
-    if (tid == 0) {
-      tau[k] = tk;
-      e[k] = beta;
-    }
+    // waves whose two tile rows lie above the trailing block have nothing to do this step
+    // (they stay idle from here on and contribute zeros to the reductions)
+    const bool wact = 8 * wave + 7 >= k + 1;
     if (rb == (k >> 2) && cb == (k >> 2)) {
 #pragma unroll
       for (int a = 0; a < 4; ++a)
         if (a == (k & 3)) d[k] = ta[a][a];
     }
-    // waves whose two tile rows lie above the trailing block have nothing to do this step
-    const bool wact = 8 * wave + 7 >= k + 1;
-    double vr[4], vc[4];
+    double vr[4], vc[4], K = 0.0;
+    if (wact) {
+      double sigma = 0.0;
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const int R = 4 * rb + a, C = 4 * cb + a;
-      vr[a] = (R == k + 1) ? 1.0 : ((R > k + 1 && R < n) ? colbuf[R] * scal : 0.0);
-      vc[a] = (C == k + 1) ? 1.0 : ((C > k + 1 && C < n) ? colbuf[C] * scal : 0.0);
-    }
-    // v_k is kept in row k of the LDS matrix, which is free during this phase (a global store
-    // here would make every barrier wait for it)
-    if (cb == 0) {
+      for (int w = 0; w < kT / 64; ++w) sigma += red[w];
+      const double x0 = colbuf[k + 1];
+      double tk = 0.0, beta = x0, scal = 0.0;
+      if (sigma != 0.0) {
+        const double mu0 = sqrt(x0 * x0 + sigma);
+        beta = (x0 <= 0.0) ? mu0 : -mu0;
+        tk = (beta - x0) * rcp2(beta);
+        scal = rcp2(x0 - beta);
+      }
+      if (tid == kT - 64) {  // the last wave is never idle
+        tau[k] = tk;
+        e[k] = beta;
+      }
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
-        const int R = 4 * rb + a;
-        if (R >= k + 1 && R < n) A[k * kS + (R - k - 1)] = vr[a];
+        const int R = 4 * rb + a, C = 4 * cb + a;
+        vr[a] = (R == k + 1) ? 1.0 : ((R > k + 1 && R < n) ? colbuf[R] * scal : 0.0);
+        vc[a] = (C == k + 1) ? 1.0 : ((C > k + 1 && C < n) ? colbuf[C] * scal : 0.0);
       }
-    }
-    // p = tau A22 v on the own rows: partial over the own columns, summed over the half-wave
-    double pp[4] = {0.0, 0.0, 0.0, 0.0};
-    if (wact) {  // uniform per wave: the DPP sums need every lane
+      // v_k is kept in row k of the LDS matrix, which is free during this phase (a global
+      // store here would make every barrier wait for it)
+      if (cb == 0) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const int R = 4 * rb + a;
+          if (R >= k + 1 && R < n) A[k * kS + (R - k - 1)] = vr[a];
+        }
+      }
+      // p = tau A22 v on the own rows: partial over the own columns, summed over the half-wave
+      double pp[4];
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
         double acc = 0.0;
@@ -248,27 +251,30 @@ __global__ __launch_bounds__(kT) void syev_kernel(const double* G, int ldg, int 
         for (int b = 0; b < 4; ++b) acc += ta[a][b] * vc[b];
         pp[a] = half_sum_to_last(acc);
       }
-    }
-    double pvp = 0.0;
-    if (wact && cb == 31) {
+      double pvp = 0.0;
+      if (cb == 31) {
 #pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        const int R = 4 * rb + a;
-        if (R >= k + 1 && R < n) {
-          const double pr = tk * pp[a];
-          pw[R] = pr;
-          pvp += pr * vr[a];
+        for (int a = 0; a < 4; ++a) {
+          const int R = 4 * rb + a;
+          if (R >= k + 1 && R < n) {
+            const double pr = tk * pp[a];
+            pw[R] = pr;
+            pvp += pr * vr[a];
+          }
         }
       }
+      const double wpv = readlane_d(pvp, 31) + readlane_d(pvp, 63);
+      if (lane == 0) red2[wave] = wpv;
+      K = tk;
+    } else if (lane == 0) {
+      red2[wave] = 0.0;
     }
-    const double wpv = readlane_d(pvp, 31) + readlane_d(pvp, 63);
-    if (lane == 0) red2[wave] = wpv;
     __syncthreads();  // (A)
-    double K = 0.0;
-#pragma unroll
-    for (int w = 0; w < kT / 64; ++w) K += red2[w];
-    K *= 0.5 * tk;
     if (wact) {
+      double pv = 0.0;
+#pragma unroll
+      for (int w = 0; w < kT / 64; ++w) pv += red2[w];
+      K *= 0.5 * pv;
       double wr[4], wc[4];
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
@@ -280,25 +286,27 @@ __global__ __launch_bounds__(kT) void syev_kernel(const double* G, int ldg, int 
       for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) ta[a][b] -= vr[a] * wc[b] + wr[a] * vc[b];
-    }
-    // column k+1 into colbuf and the next step's sum of squares (owners: cb == (k+1)/4)
-    const int cbn = (k + 1) >> 2, bn = (k + 1) & 3;
-    double part = 0.0;
-    if (cb == cbn) {
+      // column k+1 into colbuf and the next step's sum of squares (owners: cb == (k+1)/4)
+      const int cbn = (k + 1) >> 2, bn = (k + 1) & 3;
+      double part = 0.0;
+      if (cb == cbn) {
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        if (b == bn) {
+        for (int b = 0; b < 4; ++b) {
+          if (b == bn) {
 #pragma unroll
-          for (int a = 0; a < 4; ++a) {
-            const int R = 4 * rb + a;
-            colbuf[R] = ta[a][b];
-            if (R >= k + 3 && R < n) part += ta[a][b] * ta[a][b];
+            for (int a = 0; a < 4; ++a) {
+              const int R = 4 * rb + a;
+              colbuf[R] = ta[a][b];
+              if (R >= k + 3 && R < n) part += ta[a][b] * ta[a][b];
+            }
           }
         }
       }
+      const double wpart = readlane_d(part, cbn) + readlane_d(part, 32 + cbn);
+      if (lane == 0) red[wave] = wpart;
+    } else if (lane == 0) {
+      red[wave] = 0.0;
     }
-    const double wpart = readlane_d(part, cbn) + readlane_d(part, 32 + cbn);
-    if (lane == 0) red[wave] = wpart;
     __syncthreads();  // (B)
   }
   // the last 2 x 2 block
@@ -562,9 +570,10 @@ __global__ __launch_bounds__(kT) void syev_kernel(const double* G, int ldg, int 
     }
   }
   if (tid == 0) {
-    int any = 0, ngs = 0;
+    int any = 0, ngs = 0, nslot = 0;
     for (int g = 0; g < n; ++g) {
       any |= incl[g];
+      slot_s[g] = incl[g] ? nslot++ : -1;
       if (incl[g] && cl0[g] < g) gs_list[ngs++] = g;
     }
     sh_int[1] = any;
@@ -582,7 +591,9 @@ __global__ __launch_bounds__(kT) void syev_kernel(const double* G, int ldg, int 
         // relative accuracy (an absolute floor would mix in neighbouring eigenvectors)
         const double pfl = fmax(kEps * lam, pivmin);
         double* z = A + g;
-        double* lp = lwork + (size_t)g * kMaxL;
+        // L+ of this column's solve: LDS for the first clustered columns, else global scratch
+        const int sl = slot_s[g];
+        double* lp = (sl < kLdsSlots) ? lds_lp + sl * kMaxL : lwork + (size_t)g * kMaxL;
         double s = -lam, yprev = 0.0, lprev = 0.0;
         for (int i = o; i <= last; ++i) {
           const double dp = guard(Dr[i] + s, pfl);
@@ -596,7 +607,7 @@ __global__ __launch_bounds__(kT) void syev_kernel(const double* G, int ldg, int 
             s = lprev * Lr[i] * s - lam;
           }
         }
-        double ynext = z[last * kS], ymax = fabs(ynext);
+        double ynext = z[last * kS], ymax = fabs(ynext), nrm = ynext * ynext;
         for (int i = last - 1; i >= o; i -= 8) {
           // the L+ values come from global memory: fetch eight before the dependent chain
           double lv[8];
@@ -609,18 +620,22 @@ __global__ __launch_bounds__(kT) void syev_kernel(const double* G, int ldg, int 
               z[(i - u) * kS] = y;
               ynext = y;
               ymax = fmax(ymax, fabs(y));
+              nrm += y * y;
             }
           }
         }
-        if (ymax > 0.0) {  // scale first: the solve output can be far from 1 in magnitude
+        if (nrm > 0.0 && nrm <= 1e300) {
+          const double inv = 1.0 / sqrt(nrm);
+          for (int i = o; i <= last; ++i) z[i * kS] *= inv;
+        } else if (ymax > 0.0) {  // sum of squares out of range: scale by the largest entry first
           const double sc = 1.0 / ymax;
-          double nrm = 0.0;
+          double nrm2 = 0.0;
           for (int i = o; i <= last; ++i) {
             const double y = z[i * kS] * sc;
             z[i * kS] = y;
-            nrm += y * y;
+            nrm2 += y * y;
           }
-          const double inv = 1.0 / sqrt(nrm);
+          const double inv = 1.0 / sqrt(nrm2);
           for (int i = o; i <= last; ++i) z[i * kS] *= inv;
         }
       }

@@ -111,6 +111,48 @@ def test_spmm_float_parity_power_law(trans, l):
 
 
 @pytest.mark.parametrize("trans", [0, 1])
+def test_spmm_width_not_multiple_of_4(trans):
+    # 14 computed columns: the two-column-per-lane kernel instead of the paired 16-byte one
+    A = zipf_lognormal(m=30_011, n=4_003, t=20)
+    rows_in = A.m if trans else A.n
+    X = np.random.default_rng(5).standard_normal((rows_in, 13))
+    say("spmm width 14", trans, A.m, A.n, A.nnz)
+    mat = _mat(A)
+    got = _spmm(mat, trans, X, 14)[:, :13]
+    Xf = X.astype(np.float32).astype(np.float64)
+    ref = oracle.csr_tmatmul(A, Xf) if trans else oracle.csr_matmul(A, Xf)
+    absA = A.to_scipy()
+    absA.data = np.abs(absA.data)
+    bound = (absA.T if trans else absA) @ np.abs(Xf)
+    assert np.all(np.abs(got - ref) <= 1e-5 * bound + 1e-30)
+
+
+@pytest.mark.parametrize("layout", ["all_hot", "no_hot", "mixed"])
+def test_transpose_product_layouts(layout):
+    """A^T Y through the row-blocked order when every column is frequent (no tail part), when
+    none is (plain column order), and for a mix over several row blocks; exact on integers."""
+    if layout == "all_hot":
+        A = random_sparse(3000, 50, 0.3, seed=21, integer_values=True)
+    elif layout == "no_hot":
+        A = random_sparse(20_000, 20_000, 1e-4, seed=22, integer_values=True)
+    else:
+        A = random_sparse(30_000, 700, 0.02, seed=23, empty_cols=(3, 699), integer_values=True)
+    Y = np.random.default_rng(6).integers(-8, 9, size=(A.m, 60)).astype(np.float64)
+    say("transpose layout", layout, A.m, A.n, A.nnz)
+    mat = _mat(A)
+    info = mat.info()
+    if layout == "all_hot":
+        assert info["hot_cols"] == A.n and info["hot_nnz"] == A.nnz
+    elif layout == "no_hot":
+        assert info["hot_cols"] == 0
+    else:
+        assert 0 < info["hot_cols"] < A.n and info["row_blocks"] == 8
+    got = _spmm(mat, 1, Y, 64)
+    assert np.array_equal(got[:, :60], oracle.csr_tmatmul(A, Y))
+    assert np.all(got[:, 60:] == 0)
+
+
+@pytest.mark.parametrize("trans", [0, 1])
 def test_spmm_bf16_panels(trans):
     A = random_sparse(4000, 3000, 0.01, seed=12)
     rows_in = A.m if trans else A.n
