@@ -75,6 +75,67 @@ __global__ __launch_bounds__(256) void sddmm_kernel(const int32_t* rp, const int
   }
 }
 
+// Paired form (k a multiple of 4, rows 16-byte aligned): lanes 0-31 take the even nonzero of
+// each pair of a row, lanes 32-63 the odd one, a lane covering four columns; eight pairs are
+// gathered before any is reduced, and each half-wave sum runs on DPP row shifts (lanes 31 and
+// 63 end with the totals), so no LDS shuffles are needed.
+constexpr int kSdPairs = 8;
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dppf(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, true));
+}
+
+// Sum over each half-wave, valid in lanes 31 and 63 (row shifts 1, 2, 4, 8 then the row-15
+// broadcast into rows 1 and 3; out-of-row sources read 0).
+__device__ __forceinline__ float half_sum_last(float v) {
+  v += dppf<0x111, 0xF>(v);
+  v += dppf<0x112, 0xF>(v);
+  v += dppf<0x114, 0xF>(v);
+  v += dppf<0x118, 0xF>(v);
+  v += dppf<0x142, 0xA>(v);
+  return v;
+}
+
+__global__ __launch_bounds__(256) void sddmm4_kernel(const int32_t* rp, const int32_t* col, int64_t m, int w,
+                                                     const float* P1, const float* Q1, const float* P2,
+                                                     const float* Q2, float* dval) {
+  const int lane = threadIdx.x & 63, half = lane >> 5;
+  const int c4 = 4 * (lane & 31);
+  const bool act = c4 < w;
+  const int gc = act ? c4 : 0;
+  const int64_t wave0 = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t wstride = (int64_t)gridDim.x * 4;
+  for (int64_t r = wave0; r < m; r += wstride) {
+    float4 x = make_float4(0.f, 0.f, 0.f, 0.f), y = x;
+    if (act) x = *reinterpret_cast<const float4*>(P1 + (size_t)r * w + c4);
+    if (P2 && act) y = *reinterpret_cast<const float4*>(P2 + (size_t)r * w + c4);
+    const int e0 = rp[r], e1 = rp[r + 1];
+    for (int e = e0; e < e1; e += 2 * kSdPairs) {
+      float part[kSdPairs];
+#pragma unroll
+      for (int p = 0; p < kSdPairs; ++p) {
+        const int ee = e + 2 * p + half;
+        const bool ok = ee < e1;
+        const int c = ok ? col[ee] : 0;
+        const float4 q = *reinterpret_cast<const float4*>(Q1 + (size_t)c * w + gc);
+        float s = x.x * q.x + x.y * q.y + x.z * q.z + x.w * q.w;
+        if (Q2) {
+          const float4 q2 = *reinterpret_cast<const float4*>(Q2 + (size_t)c * w + gc);
+          s += y.x * q2.x + y.y * q2.y + y.z * q2.z + y.w * q2.w;
+        }
+        part[p] = (ok && act) ? s : 0.f;
+      }
+#pragma unroll
+      for (int p = 0; p < kSdPairs; ++p) {
+        const float t = half_sum_last(part[p]);
+        const int ee = e + 2 * p + half;
+        if ((lane & 31) == 31 && ee < e1) dval[ee] = t;
+      }
+    }
+  }
+}
+
 }  // namespace
 
 void launch_adjoint_small(const double* J, const double* K, const float* S, const float* dS, int k, bool has_du,
@@ -87,6 +148,11 @@ void launch_sddmm(const int32_t* rp, const int32_t* col, int64_t m, int w, const
   if (m <= 0) return;
   int64_t grid = (m + 3) / 4;
   if (grid > 65536) grid = 65536;
+  auto al = [](const float* p) { return p == nullptr || (reinterpret_cast<uintptr_t>(p) % 16) == 0; };
+  if (w % 4 == 0 && w <= 128 && al(P1) && al(Q1) && al(P2) && al(Q2)) {
+    sddmm4_kernel<<<(unsigned)grid, 256, 0, st>>>(rp, col, m, w, P1, Q1, P2, Q2, dval);
+    return;
+  }
   sddmm_kernel<<<(unsigned)grid, 256, 0, st>>>(rp, col, m, w, P1, Q1, P2, Q2, dval);
 }
 

@@ -19,10 +19,13 @@ def _rows(A):
     return np.repeat(np.arange(A.m), np.diff(A.row_ptr))
 
 
-def test_backward_matches_fp64_formula_at_gpu_factors():
-    A = zipf_normal(m=20_000, n=4_000, t=30)
-    k, q, s = 25, 4, 10
-    say("backward formula", A.m, A.n, A.nnz)
+@pytest.mark.parametrize("k,t", [(25, 30), (24, 31)])
+def test_backward_matches_fp64_formula_at_gpu_factors(k, t):
+    # k = 24 runs the paired 16-byte SDDMM (odd row lengths leave a single last entry);
+    # k = 25 the two-column-per-lane form
+    A = zipf_normal(m=20_000, n=4_000, t=t)
+    q, s = 4, 10
+    say("backward formula", k, A.m, A.n, A.nnz)
     mat = FrPCA.from_csr(A, device=DEV)
     U, S, V = mat.run(k, q, s, 11)
     rng = np.random.default_rng(0)
