@@ -6,7 +6,7 @@
 // candidate sets (4 l <= 512 rows) are merged by GEPP again until one set remains. The
 // root's GEPP fixes the pivot order and which columns have a usable pivot (best remaining
 // |entry| > tol * max|X|; inner nodes only skip exactly-zero columns). A final kernel factors
-// the pivot rows (no further pivoting needed) in FP64, inverts U in place and scatters U^-1
+// the pivot rows (no further pivoting needed) in FP64, inverts U and scatters U^-1
 // into an l x l coefficient matrix B (zero rows/columns for columns without a pivot), so
 // Q = X B runs on the MFMA panel kernel. Any pivot choice gives a P^T L spanning range(X)
 // (Lemma 3); the pivot rows of Q form a unit lower-triangular block.
@@ -45,6 +45,18 @@ __device__ __forceinline__ uint32_t wave_max_key(uint32_t k) {
   return max(max(a, b), max(c, d));
 }
 
+// Ends each branch of a selection over register-array elements by a uniform index: without
+// it the compiler merges the branches into one dynamically indexed access, which moves the
+// whole array to scratch memory.
+#define FRPCA_KEEP_BRANCH() asm volatile("")
+
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
 struct SelectArgs {
   const float* X;
   int ldx;
@@ -68,6 +80,7 @@ __global__ __launch_bounds__(kNode) void lu_select_kernel(SelectArgs a) {
   __shared__ float red_v[kWaves];
   __shared__ __align__(16) uint32_t red_k[2][kWaves];
   __shared__ int cand[kNode];
+  __shared__ int sel_s[kMaxL], col_s[kMaxL];  // chosen rows and their columns, written out at the end
   __shared__ int ncand_s;
   __shared__ float thr_s;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -185,8 +198,8 @@ __global__ __launch_bounds__(kNode) void lu_select_kernel(SelectArgs a) {
 #pragma unroll
             for (int c = 0; c < LP; c += 4) pr4[c / 4] = make_float4(row[c], row[c + 1], row[c + 2], row[c + 3]);
             act = false;
-            a.sel_out[node * kMaxL + cnt] = myrow;
-            a.col_out[node * kMaxL + cnt] = j;
+            sel_s[cnt] = myrow;
+            col_s[cnt] = j;
           }
           __syncthreads();
           if (act) {
@@ -218,26 +231,38 @@ __global__ __launch_bounds__(kNode) void lu_select_kernel(SelectArgs a) {
 #pragma unroll
     for (int c = LP - 8; c < LP; ++c) row[c] = 0.f;
   }
+  __syncthreads();
+  if (t < cnt) {
+    a.sel_out[node * kMaxL + t] = sel_s[t];
+    a.col_out[node * kMaxL + t] = col_s[t];
+  }
   if (t == 0) a.cnt_out[node] = cnt;
 }
 
-// Factor the root's pivot rows without further pivoting in FP64, invert U in place and
-// scatter U^-1 into B (l x ldb). One workgroup of 1024 threads on an r x r block in LDS with an
-// odd row stride (kMS doubles):
-//  * Doolittle: at step s the multipliers of column s are formed, then the trailing block is
-//    updated by 8 row phases x 128 columns (a wave covers 64 consecutive columns of one row).
-//  * U^-1 column by column (T[j][j] = 1/U[j][j], T[0:j, j] = -T[j][j] T[0:j, 0:j] U[0:j, j],
-//    the already inverted leading block in place): eight lanes per row share each dot product.
+// Factor the root's pivot rows without further pivoting in FP64, invert U and scatter U^-1
+// into B (l x ldb). One workgroup of 1024 threads: wave w holds columns 8 w .. 8 w + 7 and lane
+// L rows 2 L, 2 L + 1 of the r x r block, in registers.
+//  * Doolittle: the wave owning column s forms the multipliers of step s and leaves them in
+//    LDS; after one barrier every wave with live columns takes row s from lane s / 2 with
+//    readlane and updates. The owner of column s + 1 updates it first and publishes step s + 1
+//    before the rest of its update. The multipliers are not kept (only U is needed).
+//  * U goes to LDS; U^-1 by Gauss-Jordan on [U | I] from the last column back: row s of the
+//    right block is scaled by 1/U[s][s] and removed from the rows above with the factors
+//    U[i][s]. Each wave owns its columns of the right block and reads only U, so this phase
+//    needs no barrier; a wave starts at the first step that touches its columns.
 constexpr int kMS = kMaxL + 1;
 constexpr int kFT = 1024;
+constexpr int kFC = 8;  // columns per wave
+
 __global__ __launch_bounds__(kFT) void lu_factor_kernel(const float* X, int ldx, int l, const int32_t* sel,
                                                         const int32_t* selcol, const int32_t* cnt_p, double* B,
                                                         int ldb, int* ndropped) {
   __shared__ double M[kMaxL * kMS];
+  __shared__ __align__(16) double mcol[2][kMaxL];
   __shared__ int colpos[kMaxL];
   __shared__ int colid[kMaxL];
   __shared__ int selrow[kMaxL];
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int r = *cnt_p;
   if (t < kMaxL) colpos[t] = -1;
   __syncthreads();
@@ -247,39 +272,116 @@ __global__ __launch_bounds__(kFT) void lu_factor_kernel(const float* X, int ldx,
     selrow[t] = sel[t];
   }
   __syncthreads();
-  for (int idx = t; idx < r * r; idx += kFT) {
-    const int i = idx / r, j = idx - i * r;
-    M[i * kMS + j] = (double)X[(size_t)selrow[i] * ldx + colid[j]];
+  const int cb = kFC * w;
+  double u[2][kFC];
+  static_for<0, 2>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    const int row = 2 * lane + i;
+    static_for<0, kFC>([&](auto cc) {
+      constexpr int c = decltype(cc)::value;
+      u[i][c] = (row < r && cb + c < r) ? (double)X[(size_t)selrow[row] * ldx + colid[cb + c]] : 0.0;
+    });
+  });
+  // multipliers of step s from column s's values colv (this lane's two rows) by its owner
+  auto publish = [&](int s, const double (&colv)[2]) {
+    const double mine = (s & 1) ? colv[1] : colv[0];
+    const double rp = 1.0 / readlane_d(mine, s >> 1);
+    double2 m;
+    m.x = 2 * lane > s ? colv[0] * rp : 0.0;
+    m.y = 2 * lane + 1 > s ? colv[1] * rp : 0.0;
+    reinterpret_cast<double2*>(mcol[s & 1])[lane] = m;
+  };
+  if (w == 0 && r > 1) {
+    const double colv[2] = {u[0][0], u[1][0]};
+    publish(0, colv);
   }
-  __syncthreads();
-  const int c = t & (kMaxL - 1), g = t >> 7;  // column, row phase 0..7
+#pragma unroll 1
   for (int s = 0; s + 1 < r; ++s) {
-    if (t > s && t < r) M[t * kMS + s] /= M[s * kMS + s];
     __syncthreads();
-    if (c > s && c < r) {
-      const double us = M[s * kMS + c];
-      for (int i = s + 1 + g; i < r; i += 8) M[i * kMS + c] -= M[i * kMS + s] * us;
+    if (w < s / kFC) continue;
+    const double2 m = reinterpret_cast<const double2*>(mcol[s & 1])[lane];
+    double prow[kFC];
+    const int pl = s >> 1;
+    if (s & 1) {
+      static_for<0, kFC>([&](auto cc) { prow[decltype(cc)::value] = readlane_d(u[1][decltype(cc)::value], pl); });
+      FRPCA_KEEP_BRANCH();
+    } else {
+      static_for<0, kFC>([&](auto cc) { prow[decltype(cc)::value] = readlane_d(u[0][decltype(cc)::value], pl); });
+      FRPCA_KEEP_BRANCH();
     }
-    __syncthreads();
-  }
-  {
-    const int i = t >> 3, part = t & 7;
-    for (int j = 0; j < r; ++j) {
-      double y = 0.0;
-      if (i < j) {
-        const double* Ti = M + i * kMS;
-        for (int k = i + part; k < j; k += 8) y += Ti[k] * M[k * kMS + j];
-      }
-      y += __shfl_xor(y, 1);
-      y += __shfl_xor(y, 2);
-      y += __shfl_xor(y, 4);
-      const double djj = 1.0 / M[j * kMS + j];
-      __syncthreads();  // every read of column j precedes the writes below
-      if (i < j && part == 0) M[i * kMS + j] = -djj * y;
-      if (t == 0) M[j * kMS + j] = djj;
-      __syncthreads();
+    auto upd = [&](auto cc) {
+      constexpr int c = decltype(cc)::value;
+      u[0][c] = fma(-m.x, prow[c], u[0][c]);
+      u[1][c] = fma(-m.y, prow[c], u[1][c]);
+    };
+    const int sn = s + 1, nc = sn % kFC;
+    const bool own_next = sn + 1 < r && w == sn / kFC;
+    if (own_next) {
+      double colv[2];
+      static_for<0, kFC>([&](auto cc) {
+        if (nc == decltype(cc)::value) {
+          upd(cc);
+          colv[0] = u[0][decltype(cc)::value];
+          colv[1] = u[1][decltype(cc)::value];
+          FRPCA_KEEP_BRANCH();
+        }
+      });
+      publish(sn, colv);
     }
+    const int skip = own_next ? nc : -1;
+    static_for<0, kFC>([&](auto cc) {
+      if (decltype(cc)::value != skip) upd(cc);
+    });
   }
+  // U (upper triangle) to LDS
+  static_for<0, 2>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    const int row = 2 * lane + i;
+    static_for<0, kFC>([&](auto cc) {
+      constexpr int c = decltype(cc)::value;
+      if (row < r && cb + c < r) M[row * kMS + cb + c] = u[i][c];
+    });
+  });
+  __syncthreads();
+  double tt[2][kFC];
+  static_for<0, 2>([&](auto ic) {
+    static_for<0, kFC>([&](auto cc) {
+      tt[decltype(ic)::value][decltype(cc)::value] =
+          (2 * lane + decltype(ic)::value == cb + decltype(cc)::value) ? 1.0 : 0.0;
+    });
+  });
+  // columns cb .. cb + 7 of U^-1 are zero above... below row cb + 7: steps s > cb + 7 leave them alone
+#pragma unroll 1
+  for (int s = min(r - 1, cb + kFC - 1); s >= 0; --s) {
+    const double rinv = 1.0 / M[s * kMS + s];
+    const double f0 = 2 * lane < s ? M[(2 * lane) * kMS + s] : 0.0;
+    const double f1 = 2 * lane + 1 < s ? M[(2 * lane + 1) * kMS + s] : 0.0;
+    const int pl = s >> 1;
+    double prow[kFC];
+    if (s & 1) {
+      static_for<0, kFC>([&](auto cc) { prow[decltype(cc)::value] = readlane_d(tt[1][decltype(cc)::value], pl) * rinv; });
+      FRPCA_KEEP_BRANCH();
+    } else {
+      static_for<0, kFC>([&](auto cc) { prow[decltype(cc)::value] = readlane_d(tt[0][decltype(cc)::value], pl) * rinv; });
+      FRPCA_KEEP_BRANCH();
+    }
+    const bool mine0 = 2 * lane == s, mine1 = 2 * lane + 1 == s;
+    static_for<0, kFC>([&](auto cc) {
+      constexpr int c = decltype(cc)::value;
+      tt[0][c] = mine0 ? prow[c] : fma(-f0, prow[c], tt[0][c]);
+      tt[1][c] = mine1 ? prow[c] : fma(-f1, prow[c], tt[1][c]);
+    });
+  }
+  __syncthreads();  // every wave is done reading U
+  static_for<0, 2>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    const int row = 2 * lane + i;
+    static_for<0, kFC>([&](auto cc) {
+      constexpr int c = decltype(cc)::value;
+      if (row < r && cb + c < r) M[row * kMS + cb + c] = tt[i][c];
+    });
+  });
+  __syncthreads();
   for (int idx = t; idx < l * ldb; idx += kFT) {
     const int a = idx / ldb, b = idx - a * ldb;
     double v = 0.0;
