@@ -4,11 +4,13 @@
 // is out[i, :] = sum val * in[idx, :]. CSR rows give A Q; the column-major mirror gives
 // A^T Y, so the transpose product needs no atomics. Work is split by merge path (Merrill &
 // Garland, SC'16): each wave owns an equal share of (nonzeros + segment ends), which keeps
-// power-law columns with millions of entries balanced. A lane owns two panel columns
-// (float2), so a wave streams one 2*64-wide panel row per nonzero; the (index, value)
-// stream is read 64 entries per coalesced load and broadcast with readlane. Partial sums of segments cut by a partition
-// boundary go to per-wave carry/head slots and a fix-up kernel adds them in wave order,
-// so results are deterministic.
+// power-law columns with millions of entries balanced. The (index, value) stream is read 64
+// entries per coalesced load and broadcast with readlane. In the basic form a lane owns two
+// panel columns (float2), so a wave gathers one panel row per nonzero; panels whose rows
+// are 16-byte aligned with a computed width that is a multiple of 4 take the paired form
+// further down, where one 16-byte load per lane fetches two panel rows. Partial sums of
+// segments cut by a partition boundary go to per-wave carry/head slots and a fix-up kernel
+// adds them in wave order, so results are deterministic.
 #include <climits>
 
 #include "kernels.h"

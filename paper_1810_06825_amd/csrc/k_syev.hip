@@ -4,10 +4,13 @@
 // back-transformation:
 //
 //  1. Q^T G Q = T by Householder reflectors H_k = I - tau_k v_k v_k^T, v_k(0) = 1 (Golub &
-//     Van Loan, Alg. 8.3.1). G lives in LDS; step k needs three barriers: v_k (with the norm
-//     of the next column reduced during the previous update), p = tau A22 v with p.v, and
-//     the rank-2 update A22 -= v w^T + w v^T, w = p - (tau p.v / 2) v. The v_k go to a global
-//     scratch buffer for step 5.
+//     Van Loan, Alg. 8.3.1). G lives in registers as 4 x 4 tiles (thread t holds rows
+//     4 (t / 32).., columns 4 (t % 32)..), so sums over a row are half-wave DPP reductions.
+//     Step k takes two barriers: one after v_k and the partial products p = tau A22 v, one
+//     after the rank-2 update A22 -= v w^T + w v^T, w = p - (tau p.v / 2) v, during which the
+//     owners of column k + 1 also reduce its norm for the next step. Waves whose tiles lie
+//     wholly in the finished part skip the work. The v_k stay in LDS during the phase and
+//     then go to a global scratch buffer for step 5.
 //  2. T splits where |e_j| <= eps ||T||. Each unreduced block gets a root representation
 //     L D L^T = T - sigma I with every D_i > 0. For a Gram matrix sigma = -nb eps ||T_b||
 //     works; otherwise sigma is the smallest eigenvalue (multisection on Sturm counts of T)
@@ -15,17 +18,19 @@
 //     eigenvalues to high relative accuracy, so eigenvectors of eigenvalues with a relative
 //     gap of 1e-3 or more come out numerically orthogonal without any reorthogonalization.
 //  3. Eigenvalues mu of L D L^T by multisection on negative-pivot counts of the stationary
-//     qd transform L D L^T - x I = L+ D+ L+^T (eight threads per eigenvalue, nine
-//     subintervals per step, geometric points while the bracket spans a wide ratio), to a
-//     relative width of 4 eps.
+//     qd transform L D L^T - x I = L+ D+ L+^T (four lanes per eigenvalue, five subintervals
+//     per step, geometric points while the bracket spans a wide ratio, reciprocals by the
+//     hardware estimate and two Newton steps), to a relative width of 4 eps.
 //  4. Each isolated eigenvector from the twisted factorization of L D L^T - mu I at the index
 //     r where |gamma_r| = |s_r + p_r + mu| is smallest (stationary and progressive qd
 //     transforms): z_r = 1, z_i = -L+_i z_i+1 above r, z_i+1 = -U-_i z_i below r. Eigenvalues
 //     with a relative gap under 1e-3 form clusters; their vectors start from the twisted
 //     ones (slightly perturbed) and take three steps of inverse iteration with shifts kept
 //     10 eps apart, each followed by Gram-Schmidt (twice) against the earlier members.
-//  5. W = H_0 H_1 ... H_{n-3} Z, eigenvalues sorted ascending (the order Alg. 2 and the final
-//     selection ind = k+s:-1:s+1 rely on; ties in index order).
+//  5. W = H_0 H_1 ... H_{n-3} Z with Z in registers (each wave owns eight columns) and the
+//     reflectors staged in LDS, so every wave applies all of them to its own columns with no
+//     barrier; eigenvalues sorted ascending (the order Alg. 2 and the final selection
+//     ind = k+s:-1:s+1 rely on; ties in index order).
 #include "kernels.h"
 
 namespace frpca {
