@@ -91,6 +91,7 @@ struct frpca_ctx {
   bool has_bcsc = false;
   MergePlan bhotp, btailp;  // hot segments (sweep mode) and tail columns
   int32_t *bptr = nullptr, *bptr_tail = nullptr, *brow = nullptr, *bperm = nullptr, *colmap = nullptr;
+  int32_t *bhotcol = nullptr, *btailcol = nullptr;  // hot / tail index -> column
   float* bval = nullptr;
   int64_t bhot = 0, bnblk = 0, bnseg = 0;
 
@@ -212,13 +213,13 @@ struct frpca_ctx {
     launch_merge_fixplan(p, stream);
   }
 
-  // A^T in through the blocked order: merge-path into the partial rows, carry fix-up, then
-  // the fixed-order combine into out (n x ld_out)
+  // A^T in through the blocked order: the hot segments into the partial rows, the tail columns
+  // straight into their rows of out (n x ld_out), then the fixed-order combine of the hot rows
   void bcsc_product(int lp, const void* in, bool in_bf16, int ld_in, float* part, float* out32, uint16_t* out16,
                     int ld_out, hipStream_t st) {
     launch_spmm(bhotp, lp, in, in_bf16, ld_in, part, nullptr, lp, st);
-    launch_spmm(btailp, lp, in, in_bf16, ld_in, part + (size_t)bhotp.nseg * lp, nullptr, lp, st);
-    launch_bcsc_combine(part, lp, colmap, n, bhot, bnblk, lp, out32, out16, ld_out, st);
+    launch_spmm(btailp, lp, in, in_bf16, ld_in, out32, out16, ld_out, st);
+    launch_bcsc_combine(part, lp, bhotcol, bhot, bnblk, lp, out32, out16, ld_out, st);
   }
 
   int64_t short_rows() const { return std::min(m, n); }
@@ -251,7 +252,7 @@ struct frpca_ctx {
       ndrop = a.take<int>(4);
       lu_tmp = a.take<char>(lu_temp_bytes(Ns, lp));
       sign_tmp = a.take<char>(sign_partial_bytes(Nl, kMaxL));
-      bpart = has_bcsc ? a.take<float>((size_t)bnseg * lp) : nullptr;
+      bpart = has_bcsc ? a.take<float>((size_t)bhotp.nseg * lp) : nullptr;
     };
     Arena probe;
     plan(probe);
@@ -396,6 +397,9 @@ int frpca_create(frpca_t* out, int64_t m, int64_t n, int64_t nnz, const int64_t*
           h->bval = static_cast<float*>(h->alloc_owned(nnz * sizeof(float)));
           launch_colmap(static_cast<int32_t*>(hot.p), static_cast<int32_t*>(hpre.p), static_cast<int32_t*>(tpre.p),
                         n, h->colmap, st);
+          h->bhotcol = static_cast<int32_t*>(h->alloc_owned(hh * sizeof(int32_t)));
+          h->btailcol = static_cast<int32_t*>(h->alloc_owned(std::max<int64_t>(n - hh, 1) * sizeof(int32_t)));
+          launch_colmap_inverse(h->colmap, n, h->bhotcol, h->btailcol, st);
           uint32_t* bv = reinterpret_cast<uint32_t*>(h->bperm);
           launch_bcsc_keys(static_cast<int32_t*>(row_of.p), col, nnz, h->colmap, hh, nblk, kk, st);
           iota_kernel<<<(unsigned)((nnz + 255) / 256), 256, 0, st>>>(bv, nnz);
@@ -412,6 +416,7 @@ int frpca_create(frpca_t* out, int64_t m, int64_t n, int64_t nnz, const int64_t*
           h->build_plan(h->bhotp, h->bptr, h->brow, h->bval, nhs, true, nnz_hot);
           h->build_plan(h->btailp, h->bptr_tail, h->brow + nnz_hot, h->bval + nnz_hot, n - hh, false,
                         nnz - nnz_hot);
+          h->btailp.out_row = h->btailcol;  // tail segment i is column btailcol[i] of the result
           check_launch();
         }
       }
@@ -490,9 +495,9 @@ int frpca_run(frpca_t h, int k, int p_passes, int s_oversample, uint64_t seed, f
       const void* in = bf ? static_cast<const void*>(h->Yb) : static_cast<const void*>(h->Y);
       if (a6 && h->has_bcsc) {
         spmm(h->bhotp, back_cls, in, bf != 0, h->bpart, nullptr);
-        spmm(h->btailp, FRPCA_T_SPMM_TAIL, in, bf != 0, h->bpart + (size_t)h->bhotp.nseg * LP, nullptr);
+        spmm(h->btailp, FRPCA_T_SPMM_TAIL, in, bf != 0, h->X, nullptr);
         frpca_ctx::Scope t(h, FRPCA_T_SPMM_COMB);
-        launch_bcsc_combine(h->bpart, LP, h->colmap, n, h->bhot, h->bnblk, LP, h->X, nullptr, LP, st);
+        launch_bcsc_combine(h->bpart, LP, h->bhotcol, h->bhot, h->bnblk, LP, h->X, nullptr, LP, st);
       } else {
         spmm(Bp, back_cls, in, bf != 0, h->X, nullptr);
       }
@@ -696,7 +701,7 @@ int frpca_spmm(frpca_t h, int trans, int l, const void* in, int in_bf16, int ld_
     float* o32 = out_bf16 ? nullptr : static_cast<float*>(out);
     uint16_t* o16 = out_bf16 ? static_cast<uint16_t*>(out) : nullptr;
     if (trans && h->has_bcsc) {
-      DeviceTemp part((size_t)h->bnseg * lp * sizeof(float));
+      DeviceTemp part((size_t)h->bhotp.nseg * lp * sizeof(float));
       h->bcsc_product(lp, in, in_bf16 != 0, ld_in, static_cast<float*>(part.p), o32, o16, ld_out, h->stream);
       check_launch();
       FRPCA_HIP(hipStreamSynchronize(h->stream));

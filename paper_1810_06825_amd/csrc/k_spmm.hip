@@ -34,6 +34,7 @@ struct SpmmArgs {
   float* carry;
   float* head;
   int sweep;
+  const int32_t* out_row;  // output row of each segment (identity when null)
 };
 
 // Sweep mode: a grid of resident waves walks the partitions in rounds (round i covers
@@ -78,7 +79,7 @@ __device__ __forceinline__ void spmm_partition(const SpmmArgs& a, int64_t w, int
       if (pending_head) {
         store2_f32(a.head, (size_t)w * 128 + col, acc);
       } else {
-        const size_t o = (size_t)seg * a.ld_out + col;
+        const size_t o = (size_t)(a.out_row ? a.out_row[seg] : seg) * a.ld_out + col;
         if (a.out_f32) store2_f32(a.out_f32, o, acc);
         if (a.out_bf16) store2_bf16(a.out_bf16, o, acc);
       }
@@ -236,7 +237,7 @@ __device__ __forceinline__ void spmm_partition4(const SpmmArgs& a, int64_t w, in
       if (pending_head) {
         *reinterpret_cast<float4*>(a.head + (size_t)w * 128 + col) = t;
       } else {
-        const size_t o = (size_t)seg * a.ld_out + col;
+        const size_t o = (size_t)(a.out_row ? a.out_row[seg] : seg) * a.ld_out + col;
         if (a.out_f32) *reinterpret_cast<float4*>(a.out_f32 + o) = t;
         if (a.out_bf16) {
           uint2 b;
@@ -338,10 +339,12 @@ __global__ __launch_bounds__(256) void spmm_merge4_kernel(SpmmArgs a) {
   }
 }
 
-// out[c] = carry[w0] + ... + carry[w1-1] + head[w1] for segments cut by partition bounds.
+// out[c] = carry[w0] + ... + carry[w1-1] + head[w1] for segments cut by partition bounds
+// (row c of out, or row out_row[c] when the plan maps segments to output rows).
 __global__ __launch_bounds__(256) void spmm_fixup_kernel(const int32_t* part_seg, const int32_t* fix_w0,
                                                          int64_t nwaves, const float* carry, const float* head,
-                                                         float* out_f32, uint16_t* out_bf16, int ld_out, int lp) {
+                                                         float* out_f32, uint16_t* out_bf16, int ld_out, int lp,
+                                                         const int32_t* out_row) {
   const int lane = threadIdx.x & 63;
   const int64_t w1 = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (w1 >= nwaves) return;
@@ -359,7 +362,7 @@ __global__ __launch_bounds__(256) void spmm_fixup_kernel(const int32_t* part_seg
   const float2 h = *reinterpret_cast<const float2*>(head + (size_t)w1 * 128 + col);
   s.x += h.x;
   s.y += h.y;
-  const size_t o = (size_t)c * ld_out + col;
+  const size_t o = (size_t)(out_row ? out_row[c] : c) * ld_out + col;
   if (out_f32) store2_f32(out_f32, o, s);
   if (out_bf16) store2_bf16(out_bf16, o, s);
 }
@@ -370,7 +373,7 @@ void launch_spmm_main(const MergePlan& p, int lp, const void* in, bool in_bf16, 
                       uint16_t* out_bf16, int ld_out, hipStream_t st) {
   if (p.nwaves <= 0) return;
   SpmmArgs a{p.ptr, p.idx, p.val, p.part_seg, p.part_e, p.nseg, p.nwaves, in, ld_in, out_f32, out_bf16,
-             ld_out, lp, p.carry, p.head, p.sweep};
+             ld_out, lp, p.carry, p.head, p.sweep, p.out_row};
   unsigned grid = (unsigned)((p.nwaves + 3) / 4);
   if (p.sweep && grid > kSweepBlocks) grid = kSweepBlocks;
   // paired 16-byte gathers when every row of in and out starts 16-byte (FP32) or 8-byte
@@ -392,7 +395,7 @@ void launch_spmm_fixup(const MergePlan& p, int lp, float* out_f32, uint16_t* out
   if (p.nwaves <= 0) return;
   const unsigned grid = (unsigned)((p.nwaves + 3) / 4);
   spmm_fixup_kernel<<<grid, 256, 0, st>>>(p.part_seg, p.fix_w0, p.nwaves, p.carry, p.head, out_f32, out_bf16,
-                                          ld_out, lp);
+                                          ld_out, lp, p.out_row);
 }
 
 void launch_spmm(const MergePlan& p, int lp, const void* in, bool in_bf16, int ld_in, float* out_f32,

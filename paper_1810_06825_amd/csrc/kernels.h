@@ -50,8 +50,9 @@ void launch_bcsc_keys(const int32_t* row_of, const int32_t* col, int64_t nnz, co
                       int64_t hot_cols, int64_t nblk, uint32_t* keys, hipStream_t st);
 void launch_rebase(const int32_t* ptr, int64_t count, int32_t base, int32_t* out, hipStream_t st);
 // X[c] = sum over row blocks of the hot partial rows of c (fixed order), or the tail row of c.
-void launch_bcsc_combine(const float* P, int ldp, const int32_t* colmap, int64_t n, int64_t hot_cols, int64_t nblk,
-                         int lp, float* X32, uint16_t* X16, int ldx, hipStream_t st);
+void launch_colmap_inverse(const int32_t* colmap, int64_t n, int32_t* hotcol, int32_t* tailcol, hipStream_t st);
+void launch_bcsc_combine(const float* P, int ldp, const int32_t* hotcol, int64_t hot_cols, int64_t nblk, int lp,
+                         float* X32, uint16_t* X16, int ldx, hipStream_t st);
 
 // ---------------------------------------------------------------- merge-path products
 struct MergePlan {
@@ -66,6 +67,7 @@ struct MergePlan {
   int32_t* fix_w0 = nullptr;      // [nwaves] first carrying wave of the segment whose
                                   //   head ends in wave w, or -1
   int sweep = 0;                  // resident waves walk the partitions in narrow rounds
+  const int32_t* out_row = nullptr;  // [nseg] output row of each segment (identity when null)
   float* carry = nullptr;         // [nwaves*128] partial sums carried out of each wave
   float* head = nullptr;          // [nwaves*128] partial sums of continued first segments
 };
