@@ -37,7 +37,10 @@ void launch_gather_values(const int32_t* perm, const float* val, int64_t nnz, fl
 
 // ---------------------------------------------------------------- blocked column order
 // (hot columns split by blocks of 2^kBcscRowShift rows; see k_bcsc.hip)
-constexpr int kBcscRowShift = 12;
+#ifndef FRPCA_BCSC_ROW_SHIFT
+#define FRPCA_BCSC_ROW_SHIFT 12
+#endif
+constexpr int kBcscRowShift = FRPCA_BCSC_ROW_SHIFT;
 #ifndef FRPCA_HOT_PER_BLOCK
 #define FRPCA_HOT_PER_BLOCK 12
 #endif
@@ -73,7 +76,7 @@ struct MergePlan {
 };
 int64_t merge_items_per_wave(int64_t nseg, int64_t nnz);
 #ifndef FRPCA_SWEEP_IPW
-#define FRPCA_SWEEP_IPW 256
+#define FRPCA_SWEEP_IPW 384
 #endif
 constexpr int64_t kSweepItemsPerWave = FRPCA_SWEEP_IPW;  // partition size of sweep-mode plans
 void launch_merge_partition(MergePlan& p, hipStream_t st);
