@@ -171,8 +171,14 @@ void launch_tsmm(const void* X, bool x_bf16, int ldx, int64_t rows, int kdim, co
   const int nkt = (kdim + 3) / 4;
   const int nct = (c_out + 15) / 16;
   const int64_t ntiles = (rows + 15) / 16;
+  // one persistent block per compute unit (B in LDS allows only one): B is staged once per CU
+  // and every wave walks several tiles, so the next-tile prefetch keeps the MFMAs fed
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus <= 0)
+    cus = 256;
   int64_t grid = (ntiles + kTsmmWaves - 1) / kTsmmWaves;
-  if (grid > 1024) grid = 1024;
+  if (grid > cus) grid = cus;
   if (x_bf16) tsmm_dispatch<true>(nkt, nct, (unsigned)grid, a, st);
   else tsmm_dispatch<false>(nkt, nct, (unsigned)grid, a, st);
 }
