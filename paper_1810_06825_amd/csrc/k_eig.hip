@@ -32,7 +32,8 @@ __global__ __launch_bounds__(256) void final_coeffs_kernel(const double* d, cons
                                                            double rank_tol, double* Blong, double* Bshort,
                                                            float* S, int* ndropped) {
   const double smax = sqrt(fmax(d[l - 1], 0.0));
-  for (int idx = threadIdx.x; idx < l * ldb; idx += blockDim.x) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < l * ldb) {
     const int a = idx / ldb, i = idx - a * ldb;
     double bl = 0.0, bs = 0.0;
     if (i < k) {
@@ -46,21 +47,27 @@ __global__ __launch_bounds__(256) void final_coeffs_kernel(const double* d, cons
     Blong[idx] = bl;
     Bshort[idx] = bs;
   }
-  if (threadIdx.x == 0) {
-    int nd = 0;
-    for (int i = 0; i < k; ++i) {
+  if (blockIdx.x == 0) {
+    // S and the number of dropped values (k <= 128 < blockDim): per-wave ballot counts
+    __shared__ int nd_w[4];
+    const int i = threadIdx.x;
+    bool drop = false;
+    if (i < k) {
       const double s = sqrt(fmax(d[l - 1 - i], 0.0));
       const bool keep = s > rank_tol * smax && s > 0.0;
       S[i] = keep ? (float)s : 0.0f;
-      nd += !keep;
+      drop = !keep;
     }
-    *ndropped = nd;
+    const uint64_t m = __ballot(drop);
+    if ((i & 63) == 0) nd_w[i >> 6] = (int)__popcll(m);
+    __syncthreads();
+    if (i == 0) *ndropped = nd_w[0] + nd_w[1] + nd_w[2] + nd_w[3];
   }
 }
 
 // Sign convention: per column i of V (rows x k, ld k), the largest |entry| (ties: lowest
 // row). Pass 1: one partial (|v|, row) per block and column; pass 2 reduces in block order.
-constexpr int kSignRows = 256;
+constexpr int kSignRows = 32;
 
 __global__ __launch_bounds__(256) void sign_partial_kernel(const float* V, int64_t rows, int k, float* pv, int* pr) {
   const int64_t r0 = (int64_t)blockIdx.x * kSignRows;
@@ -68,6 +75,7 @@ __global__ __launch_bounds__(256) void sign_partial_kernel(const float* V, int64
   for (int i = threadIdx.x; i < k; i += blockDim.x) {
     float best = -1.0f;
     int brow = 0;
+#pragma unroll 8
     for (int64_t r = r0; r < r1; ++r) {
       const float a = fabsf(V[r * k + i]);
       if (a > best) {
@@ -134,7 +142,7 @@ void launch_eigsvd_coeffs(const double* d, const double* W, int l, int ldb, doub
 
 void launch_final_coeffs(const double* d, const double* W, int l, int k, int ldb, double rank_tol, double* Blong,
                          double* Bshort, float* S, int* ndropped, hipStream_t st) {
-  final_coeffs_kernel<<<1, 256, 0, st>>>(d, W, l, k, ldb, rank_tol, Blong, Bshort, S, ndropped);
+  final_coeffs_kernel<<<(l * ldb + 255) / 256, 256, 0, st>>>(d, W, l, k, ldb, rank_tol, Blong, Bshort, S, ndropped);
 }
 
 size_t sign_partial_bytes(int64_t rows, int k) {
