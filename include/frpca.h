@@ -46,7 +46,8 @@ extern "C" {
 #define FRPCA_T_SPMM_FIX 10 /* merge-path carry fix-up of both products               */
 #define FRPCA_T_SPMM_COMB 11 /* row-block partials of the transpose product combined   */
 #define FRPCA_T_SPMM_TAIL 12 /* transpose product, columns outside the row-block part  */
-#define FRPCA_NTIMERS 13
+#define FRPCA_T_CENTER 13 /* rank-1 terms of the centred products (opts.center)       */
+#define FRPCA_NTIMERS 14
 
 typedef struct frpca_ctx* frpca_t;
 
@@ -63,6 +64,13 @@ typedef struct {
   int timing;           /* 1: time each kernel class with HIP events (frpca_get_info). */
   size_t max_workspace; /* 0: unlimited; else frpca_run fails with FRPCA_ENOMEM if its
                            device workspace would exceed this many bytes.             */
+  int center;           /* 1: principal components of the column-centred matrix
+                           A - 1 mu^T (mu = column means of A), the PCA of data with rows
+                           as samples (Section 1 assumes centred data), without forming it:
+                           each product with A or A^T gets its rank-1 term; the column
+                           means follow frpca_set_values; frpca_backward then returns the
+                           gradient with respect to A's stored values through the
+                           centring. 0 (default): A itself.                            */
 } frpca_opts;
 
 typedef struct {

@@ -22,8 +22,12 @@ import numpy as np
 
 
 def svd_adjoint_values(U, S, V, dU, dS, dV, rows, cols, gap_tol: float = 1e-12,
-                       chunk: int = 1 << 20) -> np.ndarray:
-    """dL/dA at positions (rows[e], cols[e]) given dL/dU, dL/dS, dL/dV (None = zero)."""
+                       chunk: int = 1 << 20, center: bool = False) -> np.ndarray:
+    """dL/dA at positions (rows[e], cols[e]) given dL/dU, dL/dS, dL/dV (None = zero).
+
+    With center, U S V^T is the SVD of the column-centred matrix A - 1 mu^T (mu = column
+    means of A, m = U.shape[0] rows): that map is A -> (I - 1 1^T / m) A, so dL/dA is the
+    adjoint Abar of the centred matrix with each column's mean removed."""
     U = np.asarray(U, dtype=np.float64)
     V = np.asarray(V, dtype=np.float64)
     S = np.asarray(S, dtype=np.float64)
@@ -48,9 +52,13 @@ def svd_adjoint_values(U, S, V, dU, dS, dV, rows, cols, gap_tol: float = 1e-12,
     Us = U * sp[None, :]
     rows = np.asarray(rows, dtype=np.int64)
     cols = np.asarray(cols, dtype=np.int64)
+    P = UM + Ur                                   # Abar = P V^T + Us Vr^T
+    colmean = np.zeros(V.shape[0])
+    if center:
+        colmean = V @ P.mean(axis=0) + Vr @ Us.mean(axis=0)
     out = np.empty(rows.size)
     for a in range(0, rows.size, chunk):
         r = rows[a:a + chunk]
         c = cols[a:a + chunk]
-        out[a:a + chunk] = ((UM[r] + Ur[r]) * V[c]).sum(1) + (Us[r] * Vr[c]).sum(1)
+        out[a:a + chunk] = (P[r] * V[c]).sum(1) + (Us[r] * Vr[c]).sum(1) - colmean[c]
     return out

@@ -10,6 +10,8 @@ eigSVD of the projected matrix gives the k leading triplets, taken in the order
 ind = k+s, k+s-1, ..., s+1 because eigSVD returns ascending singular values.
 
 Readings where the paper is silent (each also applied by the GPU path):
+  * centring (option): the PCA of data with rows as samples centres the columns; the
+    products then act on A - 1 mu^T without forming it (see products());
   * orientation: m >= n runs Alg. 6, m < n runs Alg. 5 (the paper picks by shape and uses
     Alg. 6 on a square matrix in Section 4.2);
   * the Gaussian draws come from Philox4x32-10 (see philox.py); Alg. 6's randn(k+s, m)
@@ -55,13 +57,34 @@ def sign_convention(U: np.ndarray, V: np.ndarray):
     return U, V
 
 
+def products(A, center: bool = False):
+    """The two products the algorithms use, (X -> A X, Y -> A^T Y), of A itself or, with
+    center, of the column-centred matrix A - 1 mu^T (mu = column means of A, the data
+    centring the paper's PCA assumes in Section 1), written without forming it:
+    (A - 1 mu^T) X = A X - 1 (mu^T X) and (A - 1 mu^T)^T Y = A^T Y - mu (1^T Y)."""
+    if not center:
+        return (lambda X: csr_matmul(A, X)), (lambda Y: csr_tmatmul(A, Y))
+    mu = csr_tmatmul(A, np.ones((A.m, 1)))[:, 0] / A.m
+
+    def mul(X):
+        X = np.asarray(X, dtype=np.float64)
+        return csr_matmul(A, X) - (mu @ X)[None, :]
+
+    def tmul(Y):
+        Y = np.asarray(Y, dtype=np.float64)
+        return csr_tmatmul(A, Y) - np.outer(mu, Y.sum(axis=0))
+
+    return mul, tmul
+
+
 def frpcat(A, k: int, q: int, s: int, seed: int, rank_tol: float = 1e-5,
-           inner_tol: float = 1e-12):
+           inner_tol: float = 1e-12, center: bool = False):
     """Alg. 6 (frPCAt) for m >= n. Returns (U m x k, S k descending, V n x k)."""
+    mul, tmul = products(A, center)
     l = k + s
     if q % 2 == 0:
         omega_t = gaussian(seed, A.m, l)          # randn(k+s, m), stored transposed
-        Q = csr_tmatmul(A, omega_t)               # Q = (Omega A)^T
+        Q = tmul(omega_t)                         # Q = (Omega A)^T
         if q == 2:
             Q = eigsvd(Q, inner_tol)[0]
         else:
@@ -70,12 +93,12 @@ def frpcat(A, k: int, q: int, s: int, seed: int, rank_tol: float = 1e-5,
         Q = gaussian(seed, A.n, l)                # Q = randn(n, k+s)
     last = (q - 1) // 2
     for i in range(1, last + 1):
-        X = csr_tmatmul(A, csr_matmul(A, Q))      # A^T (A Q)
+        X = tmul(mul(Q))                          # A^T (A Q)
         if i == last:
             Q = eigsvd(X, inner_tol)[0]
         else:
             Q = lu_pl(X, inner_tol)[0]
-    Uh, Sh, Vh, _ = eigsvd(csr_matmul(A, Q), rank_tol)
+    Uh, Sh, Vh, _ = eigsvd(mul(Q), rank_tol)
     ind = np.arange(l - 1, s - 1, -1)             # k+s : -1 : s+1, zero-based
     U = Uh[:, ind]
     V = Q @ Vh[:, ind]
@@ -84,12 +107,13 @@ def frpcat(A, k: int, q: int, s: int, seed: int, rank_tol: float = 1e-5,
 
 
 def frpca_alg5(A, k: int, q: int, s: int, seed: int, rank_tol: float = 1e-5,
-               inner_tol: float = 1e-12):
+               inner_tol: float = 1e-12, center: bool = False):
     """Alg. 5 (frPCA) for m <= n. Returns (U m x k, S k descending, V n x k)."""
+    mul, tmul = products(A, center)
     l = k + s
     if q % 2 == 0:
         Q = gaussian(seed, A.n, l)                # Q = randn(n, k+s)
-        Q = csr_matmul(A, Q)                      # Q = A Q
+        Q = mul(Q)                                # Q = A Q
         if q > 2:
             Q = lu_pl(Q, inner_tol)[0]
         else:
@@ -98,12 +122,12 @@ def frpca_alg5(A, k: int, q: int, s: int, seed: int, rank_tol: float = 1e-5,
         Q = gaussian(seed, A.m, l)                # Q = randn(m, k+s)
     last = (q - 1) // 2
     for i in range(1, last + 1):
-        X = csr_matmul(A, csr_tmatmul(A, Q))      # A (A^T Q)
+        X = mul(tmul(Q))                          # A (A^T Q)
         if i == last:
             Q = eigsvd(X, inner_tol)[0]
         else:
             Q = lu_pl(X, inner_tol)[0]
-    Uh, Sh, Vh, _ = eigsvd(csr_tmatmul(A, Q), rank_tol)
+    Uh, Sh, Vh, _ = eigsvd(tmul(Q), rank_tol)
     ind = np.arange(l - 1, s - 1, -1)
     U = Q @ Vh[:, ind]
     V = Uh[:, ind]
@@ -112,17 +136,18 @@ def frpca_alg5(A, k: int, q: int, s: int, seed: int, rank_tol: float = 1e-5,
 
 
 def frpca(A, k: int, q: int, s: int, seed: int, rank_tol: float = 1e-5, inner_tol: float = 1e-12,
-          sign_fix: bool = True):
-    """Rank-k truncated SVD of sparse A by frPCA / frPCAt with q passes and oversampling s.
+          sign_fix: bool = True, center: bool = False):
+    """Rank-k truncated SVD of sparse A (or, with center, of A - 1 mu^T) by frPCA / frPCAt
+    with q passes and oversampling s.
 
     Returns (U, S, V, info) with info = {"orientation": "alg6"|"alg5", "rank_dropped": r}.
     """
     check_args(A.m, A.n, k, q, s)
     if A.m >= A.n:
-        U, S, V = frpcat(A, k, q, s, seed, rank_tol, inner_tol)
+        U, S, V = frpcat(A, k, q, s, seed, rank_tol, inner_tol, center)
         orient = "alg6"
     else:
-        U, S, V = frpca_alg5(A, k, q, s, seed, rank_tol, inner_tol)
+        U, S, V = frpca_alg5(A, k, q, s, seed, rank_tol, inner_tol, center)
         orient = "alg5"
     zero = S == 0.0
     U[:, zero] = 0.0

@@ -17,10 +17,10 @@ FRPCA_EINVAL = -1
 FRPCA_ENOMEM = -2
 FRPCA_EHIP = -3
 FRPCA_ESTATE = -4
-NTIMERS = 13
+NTIMERS = 14
 TIMER_NAMES = ("gauss", "spmm_fwd", "spmm_back", "gram", "eig", "lu", "tsmm", "sign", "bwd", "sddmm",
                "spmm_fixup", "spmm_combine",
-               "spmm_back_tail")
+               "spmm_back_tail", "center")
 
 
 class FrpcaError(RuntimeError):
@@ -31,7 +31,7 @@ class FrpcaError(RuntimeError):
 
 class FrpcaOpts(ctypes.Structure):
     _fields_ = [("panel_bf16", c_int), ("no_sign_fix", c_int), ("rank_tol", c_double),
-                ("timing", c_int), ("max_workspace", c_size_t)]
+                ("timing", c_int), ("max_workspace", c_size_t), ("center", c_int)]
 
 
 class FrpcaInfo(ctypes.Structure):

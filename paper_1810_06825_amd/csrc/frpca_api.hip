@@ -92,6 +92,11 @@ struct frpca_ctx {
   MergePlan bhotp, btailp;  // hot segments (sweep mode) and tail columns
   int32_t *bptr = nullptr, *bptr_tail = nullptr, *brow = nullptr, *bperm = nullptr, *colmap = nullptr;
   int32_t *bhotcol = nullptr, *btailcol = nullptr;  // hot / tail index -> column
+  // centred products (opts.center): column means of A, and the rank-1 term's vector with its
+  // reduction partials (k_center.hip)
+  float* mu = nullptr;
+  float* cvec = nullptr;
+  double* cpart = nullptr;
   float* bval = nullptr;
   int64_t bhot = 0, bnblk = 0, bnseg = 0;
 
@@ -253,6 +258,8 @@ struct frpca_ctx {
       lu_tmp = a.take<char>(lu_temp_bytes(Ns, lp));
       sign_tmp = a.take<char>(sign_partial_bytes(Nl, kMaxL));
       bpart = has_bcsc ? a.take<float>((size_t)bhotp.nseg * lp) : nullptr;
+      cvec = opts.center ? a.take<float>(kMaxL) : nullptr;
+      cpart = opts.center ? a.take<double>(wsum_temp_bytes(std::max(m, n)) / sizeof(double)) : nullptr;
     };
     Arena probe;
     plan(probe);
@@ -370,6 +377,10 @@ int frpca_create(frpca_t* out, int64_t m, int64_t n, int64_t nnz, const int64_t*
       check_launch();
       h->build_plan(h->csr, h->rp32, col, val, m);
       h->build_plan(h->csc, h->cp32, h->row_csc, h->val_csc, n);
+      if (h->opts.center) {
+        h->mu = static_cast<float*>(h->alloc_owned(std::max<int64_t>(n, 1) * sizeof(float)));
+        launch_colmean(h->cp32, h->val_csc, n, m, h->mu, st);
+      }
       check_launch();
       // blocked column order for the transpose product (hot columns split by row block)
       if (nnz > 0) {
@@ -448,6 +459,7 @@ int frpca_set_values(frpca_t h, const float* val) {
     h->csr.val = val;
     launch_gather_values(h->perm, val, h->nnz, h->val_csc, h->stream);
     if (h->has_bcsc) launch_gather_values(h->bperm, val, h->nnz, h->bval, h->stream);
+    if (h->opts.center) launch_colmean(h->cp32, h->val_csc, h->n, h->m, h->mu, h->stream);
     check_launch();
   });
 }
@@ -479,27 +491,50 @@ int frpca_run(frpca_t h, int k, int p_passes, int s_oversample, uint64_t seed, f
     const int fwd_cls = FRPCA_T_SPMM_F, back_cls = FRPCA_T_SPMM_B;
 
     // one product = main merge-path kernel + carry fix-up, timed as separate classes
-    auto spmm = [&](const MergePlan& p, int cls, const void* in, bool in_b, float* o32, uint16_t* o16) {
+    auto spmm = [&](const MergePlan& p, int cls, const void* in, bool in_b, float* o32, uint16_t* o16,
+                    SpmmCorr corr = {}) {
       {
         frpca_ctx::Scope t(h, cls);
-        launch_spmm_main(p, LP, in, in_b, LP, o32, o16, LP, st);
+        launch_spmm_main(p, LP, in, in_b, LP, o32, o16, LP, st, corr);
       }
       frpca_ctx::Scope t(h, FRPCA_T_SPMM_FIX);
-      launch_spmm_fixup(p, LP, o32, o16, LP, st);
+      launch_spmm_fixup(p, LP, o32, o16, LP, st, corr);
     };
+    // centred products (opts.center): the rank-1 term of (A - 1 mu^T) X is 1 (mu^T X) over the
+    // n rows of X; that of (A - 1 mu^T)^T Y is mu (1^T Y) over the m rows of Y
+    const bool cen = h->opts.center != 0;
+    auto corr_a = [&](const void* X, bool xb) -> SpmmCorr {
+      if (!cen) return {};
+      frpca_ctx::Scope t(h, FRPCA_T_CENTER);
+      launch_wsum(X, xb, LP, n, LP, h->mu, 1.0, h->cpart, h->cvec, st);
+      return {h->cvec, nullptr};
+    };
+    auto corr_at = [&](const void* Y, bool yb) -> SpmmCorr {
+      if (!cen) return {};
+      frpca_ctx::Scope t(h, FRPCA_T_CENTER);
+      launch_wsum(Y, yb, LP, m, LP, nullptr, 1.0, h->cpart, h->cvec, st);
+      return {h->cvec, h->mu};
+    };
+    // forward product (short side -> long side): A Q for Alg. 6, A^T Q for Alg. 5
+    auto forward_corr = [&](const void* in, bool in_b) { return a6 ? corr_a(in, in_b) : corr_at(in, in_b); };
     auto forward_inner = [&] {
-      if (bf) spmm(Fp, fwd_cls, h->Qb, true, nullptr, h->Yb);
-      else spmm(Fp, fwd_cls, h->Q, false, h->Y, nullptr);
+      if (bf) spmm(Fp, fwd_cls, h->Qb, true, nullptr, h->Yb, forward_corr(h->Qb, true));
+      else spmm(Fp, fwd_cls, h->Q, false, h->Y, nullptr, forward_corr(h->Q, false));
     };
-    auto back = [&] {
+    // back product (long side -> short side). For Alg. 6 the panel Y = (A - 1 mu^T) Q of a
+    // centred forward product has 1^T Y = (1^T A - m mu^T) Q = 0 exactly, so the term is
+    // skipped there (input_centred); the Gaussian start of even q has it.
+    auto back = [&](bool input_centred) {
       const void* in = bf ? static_cast<const void*>(h->Yb) : static_cast<const void*>(h->Y);
+      SpmmCorr corr{};
+      if (cen && !(a6 && input_centred)) corr = a6 ? corr_at(in, bf != 0) : corr_a(in, bf != 0);
       if (a6 && h->has_bcsc) {
         spmm(h->bhotp, back_cls, in, bf != 0, h->bpart, nullptr);
-        spmm(h->btailp, FRPCA_T_SPMM_TAIL, in, bf != 0, h->X, nullptr);
+        spmm(h->btailp, FRPCA_T_SPMM_TAIL, in, bf != 0, h->X, nullptr, corr);
         frpca_ctx::Scope t(h, FRPCA_T_SPMM_COMB);
-        launch_bcsc_combine(h->bpart, LP, h->bhotcol, h->bhot, h->bnblk, LP, h->X, nullptr, LP, st);
+        launch_bcsc_combine(h->bpart, LP, h->bhotcol, h->bhot, h->bnblk, LP, h->X, nullptr, LP, st, corr);
       } else {
-        spmm(Bp, back_cls, in, bf != 0, h->X, nullptr);
+        spmm(Bp, back_cls, in, bf != 0, h->X, nullptr, corr);
       }
     };
     auto basis_from_B1 = [&] {
@@ -533,7 +568,7 @@ int frpca_run(frpca_t h, int k, int p_passes, int s_oversample, uint64_t seed, f
         frpca_ctx::Scope t(h, FRPCA_T_GAUSS);  // long-side Gaussian (the transposed randn(k+s, .))
         launch_gaussian(seed, Nl, l, LP, bf ? nullptr : h->Y, bf ? h->Yb : nullptr, st);
       }
-      back();
+      back(false);
       if (p_passes == 2) orth_eig();
       else orth_lu();
     } else {
@@ -543,12 +578,12 @@ int frpca_run(frpca_t h, int k, int p_passes, int s_oversample, uint64_t seed, f
     const int last = (p_passes - 1) / 2;
     for (int i = 1; i <= last; ++i) {
       forward_inner();
-      back();
+      back(true);
       if (i == last) orth_eig();
       else orth_lu();
     }
     // final pass and Rayleigh-Ritz: eigSVD of the long-side panel Z
-    spmm(Fp, fwd_cls, h->Q, false, h->Z, nullptr);
+    spmm(Fp, fwd_cls, h->Q, false, h->Z, nullptr, forward_corr(h->Q, false));
     gram_eig(h->Z, Nl);
     launch_final_coeffs(h->d, h->W, l, k, LP, h->rank_tol, h->B1, h->B2, S, h->ndrop, st);
     // B1 multiplies the long-side panel Z, B2 the short-side basis Q
@@ -604,6 +639,11 @@ int frpca_backward(frpca_t h, int k, const float* U, const float* S, const float
       probe.take<double>(5 * (size_t)k * k);
       probe.take<float>((size_t)m * k);
       probe.take<float>((size_t)n * k);
+      if (h->opts.center) {
+        probe.take<double>(wsum_temp_bytes(m) / sizeof(double));
+        probe.take<float>(2 * kMaxL);
+        probe.take<float>(std::max<int64_t>(n, 1));
+      }
       if (h->opts.max_workspace && probe.used + h->setup_bytes + h->ws_bytes > h->opts.max_workspace)
         throw Error{FRPCA_ENOMEM, "backward workspace exceeds opts.max_workspace"};
       if (hipMalloc(&h->bws, probe.used) != hipSuccess) {
@@ -624,6 +664,12 @@ int frpca_backward(frpca_t h, int k, const float* U, const float* S, const float
     double* SP = a.take<double>((size_t)k * k);
     float* L1 = a.take<float>((size_t)m * k);
     float* R2 = a.take<float>((size_t)n * k);
+    // centred matrix: dA = (I - 1 1^T / m) G for the dense adjoint G = L1 V^T + U R2^T, so each
+    // row of L1 and of U loses its column mean and dval[e] drops corr[c] = l1.V[c] + lU.R2[c]
+    const bool cen = h->opts.center != 0;
+    double* wpart = cen ? a.take<double>(wsum_temp_bytes(m) / sizeof(double)) : nullptr;
+    float* ell = cen ? a.take<float>(2 * kMaxL) : nullptr;
+    float* corr = cen ? a.take<float>(std::max<int64_t>(n, 1)) : nullptr;
     {
       frpca_ctx::Scope t(h, FRPCA_T_BWD);
       if (dU) launch_gram(U, false, k, dU, k, m, k, part, J, k, st);
@@ -635,10 +681,15 @@ int frpca_backward(frpca_t h, int k, const float* U, const float* S, const float
         launch_tsmm(V, false, k, n, k, CV, k, k, k, R2, k, nullptr, 0, false, st);
         launch_tsmm(dV, false, k, n, k, SP, k, k, k, R2, k, nullptr, 0, true, st);
       }
+      if (cen) {
+        launch_wsum(L1, false, k, m, k, nullptr, 1.0 / (double)m, wpart, ell, st);
+        if (dV) launch_wsum(U, false, k, m, k, nullptr, 1.0 / (double)m, wpart, ell + kMaxL, st);
+        launch_center_corr(ell, V, ell + kMaxL, dV ? R2 : nullptr, n, k, corr, st);
+      }
     }
     {
       frpca_ctx::Scope t(h, FRPCA_T_SDDMM);
-      launch_sddmm(h->rp32, h->col, m, k, L1, V, dV ? U : nullptr, dV ? R2 : nullptr, dval, st);
+      launch_sddmm(h->rp32, h->col, m, k, L1, V, dV ? U : nullptr, dV ? R2 : nullptr, dval, st, corr);
     }
     check_launch();
   });

@@ -6,7 +6,8 @@
 //   M  = (F o (J - J^T)) S + diag(dS) + S (F o (K - K^T)),
 // is regrouped as dA = L1 V^T + U R2^T with L1 = U (M - J S+) + dU S+ and R2 = (dV - V K) S+,
 // so only its values at the stored nonzeros are formed: dval[e] = L1[r].V[c] + U[r].R2[c]
-// (sampled dense-dense product, SDDMM). The k x k algebra runs in FP64 in one workgroup.
+// (sampled dense-dense product, SDDMM), minus a per-column term corr[c] for the centred
+// matrix (k_center.hip). The k x k algebra runs in FP64 in one workgroup.
 #include "kernels.h"
 
 namespace frpca {
@@ -44,7 +45,7 @@ __global__ __launch_bounds__(256) void adjoint_small_kernel(const double* J, con
 // nonzero and reduce across the wave in a fixed butterfly order.
 __global__ __launch_bounds__(256) void sddmm_kernel(const int32_t* rp, const int32_t* col, int64_t m, int w,
                                                     const float* P1, const float* Q1, const float* P2,
-                                                    const float* Q2, float* dval) {
+                                                    const float* Q2, const float* corr, float* dval) {
   const int lane = threadIdx.x & 63;
   const int64_t wave0 = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t wstride = (int64_t)gridDim.x * 4;
@@ -70,7 +71,7 @@ __global__ __launch_bounds__(256) void sddmm_kernel(const int32_t* rp, const int
       }
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
-      if (lane == 0) dval[e] = part;
+      if (lane == 0) dval[e] = corr ? part - corr[c] : part;
     }
   }
 }
@@ -99,7 +100,7 @@ __device__ __forceinline__ float half_sum_last(float v) {
 
 __global__ __launch_bounds__(256) void sddmm4_kernel(const int32_t* rp, const int32_t* col, int64_t m, int w,
                                                      const float* P1, const float* Q1, const float* P2,
-                                                     const float* Q2, float* dval) {
+                                                     const float* Q2, const float* corr, float* dval) {
   const int lane = threadIdx.x & 63, half = lane >> 5;
   const int c4 = 4 * (lane & 31);
   const bool act = c4 < w;
@@ -113,11 +114,13 @@ __global__ __launch_bounds__(256) void sddmm4_kernel(const int32_t* rp, const in
     const int e0 = rp[r], e1 = rp[r + 1];
     for (int e = e0; e < e1; e += 2 * kSdPairs) {
       float part[kSdPairs];
+      int cs[kSdPairs];
 #pragma unroll
       for (int p = 0; p < kSdPairs; ++p) {
         const int ee = e + 2 * p + half;
         const bool ok = ee < e1;
         const int c = ok ? col[ee] : 0;
+        cs[p] = c;
         const float4 q = *reinterpret_cast<const float4*>(Q1 + (size_t)c * w + gc);
         float s = x.x * q.x + x.y * q.y + x.z * q.z + x.w * q.w;
         if (Q2) {
@@ -130,7 +133,7 @@ __global__ __launch_bounds__(256) void sddmm4_kernel(const int32_t* rp, const in
       for (int p = 0; p < kSdPairs; ++p) {
         const float t = half_sum_last(part[p]);
         const int ee = e + 2 * p + half;
-        if ((lane & 31) == 31 && ee < e1) dval[ee] = t;
+        if ((lane & 31) == 31 && ee < e1) dval[ee] = corr ? t - corr[cs[p]] : t;
       }
     }
   }
@@ -144,16 +147,16 @@ void launch_adjoint_small(const double* J, const double* K, const float* S, cons
 }
 
 void launch_sddmm(const int32_t* rp, const int32_t* col, int64_t m, int w, const float* P1, const float* Q1,
-                  const float* P2, const float* Q2, float* dval, hipStream_t st) {
+                  const float* P2, const float* Q2, float* dval, hipStream_t st, const float* corr) {
   if (m <= 0) return;
   int64_t grid = (m + 3) / 4;
   if (grid > 65536) grid = 65536;
   auto al = [](const float* p) { return p == nullptr || (reinterpret_cast<uintptr_t>(p) % 16) == 0; };
   if (w % 4 == 0 && w <= 128 && al(P1) && al(Q1) && al(P2) && al(Q2)) {
-    sddmm4_kernel<<<(unsigned)grid, 256, 0, st>>>(rp, col, m, w, P1, Q1, P2, Q2, dval);
+    sddmm4_kernel<<<(unsigned)grid, 256, 0, st>>>(rp, col, m, w, P1, Q1, P2, Q2, corr, dval);
     return;
   }
-  sddmm_kernel<<<(unsigned)grid, 256, 0, st>>>(rp, col, m, w, P1, Q1, P2, Q2, dval);
+  sddmm_kernel<<<(unsigned)grid, 256, 0, st>>>(rp, col, m, w, P1, Q1, P2, Q2, corr, dval);
 }
 
 }  // namespace frpca

@@ -67,7 +67,8 @@ __global__ void colmap_inverse_kernel(const int32_t* colmap, int64_t n, int32_t*
 constexpr int kCombWaves = 8;
 __global__ __launch_bounds__(64 * kCombWaves) void combine_hot_kernel(const float* P, int ldp, const int32_t* hotcol,
                                                                      int64_t hot_cols, int64_t nblk, int lp,
-                                                                     float* X32, uint16_t* X16, int ldx) {
+                                                                     float* X32, uint16_t* X16, int ldx,
+                                                                     const float* csub_v, const float* csub_s) {
   __shared__ float2 red[kCombWaves][64];
   const int64_t hc = blockIdx.x;
   const int q = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -90,7 +91,13 @@ __global__ __launch_bounds__(64 * kCombWaves) void combine_hot_kernel(const floa
       tot.x += red[r][lane].x;
       tot.y += red[r][lane].y;
     }
-    const size_t o = (size_t)hotcol[hc] * ldx + col;
+    const int64_t orow = hotcol[hc];
+    if (csub_v) {
+      const float sc = csub_s ? csub_s[orow] : 1.f;
+      tot.x -= sc * csub_v[col];
+      tot.y -= sc * csub_v[col + 1];
+    }
+    const size_t o = (size_t)orow * ldx + col;
     if (X32) store2_f32(X32, o, tot);
     if (X16) store2_bf16(X16, o, tot);
   }
@@ -126,10 +133,10 @@ void launch_colmap_inverse(const int32_t* colmap, int64_t n, int32_t* hotcol, in
 }
 
 void launch_bcsc_combine(const float* P, int ldp, const int32_t* hotcol, int64_t hot_cols, int64_t nblk, int lp,
-                         float* X32, uint16_t* X16, int ldx, hipStream_t st) {
+                         float* X32, uint16_t* X16, int ldx, hipStream_t st, SpmmCorr corr) {
   if (hot_cols <= 0) return;
   combine_hot_kernel<<<(unsigned)hot_cols, 64 * kCombWaves, 0, st>>>(P, ldp, hotcol, hot_cols, nblk, lp, X32, X16,
-                                                                      ldx);
+                                                                      ldx, corr.v, corr.s);
 }
 
 }  // namespace frpca

@@ -35,6 +35,8 @@ struct SpmmArgs {
   float* head;
   int sweep;
   const int32_t* out_row;  // output row of each segment (identity when null)
+  const float* csub_v;     // rank-1 term out[r] -= csub_s[r] * csub_v (none when null)
+  const float* csub_s;     //   (factor 1 when null)
 };
 
 // Sweep mode: a grid of resident waves walks the partitions in rounds (round i covers
@@ -84,9 +86,16 @@ __device__ __forceinline__ void spmm_partition(const SpmmArgs& a, int64_t w, int
       if (pending_head) {
         store2_f32(a.head, (size_t)w * 128 + col, acc);
       } else {
-        const size_t o = (size_t)(a.out_row ? a.out_row[seg] : seg) * a.ld_out + col;
-        if (a.out_f32) store2_f32(a.out_f32, o, acc);
-        if (a.out_bf16) store2_bf16(a.out_bf16, o, acc);
+        const int64_t orow = a.out_row ? a.out_row[seg] : seg;
+        float2 t = acc;
+        if (a.csub_v) {
+          const float sc = a.csub_s ? a.csub_s[orow] : 1.f;
+          t.x -= sc * a.csub_v[col];
+          t.y -= sc * a.csub_v[col + 1];
+        }
+        const size_t o = (size_t)orow * a.ld_out + col;
+        if (a.out_f32) store2_f32(a.out_f32, o, t);
+        if (a.out_bf16) store2_bf16(a.out_bf16, o, t);
       }
     }
     pending_head = false;
@@ -242,7 +251,16 @@ __device__ __forceinline__ void spmm_partition4(const SpmmArgs& a, int64_t w, in
       if (pending_head) {
         *reinterpret_cast<float4*>(a.head + (size_t)w * 128 + col) = t;
       } else {
-        const size_t o = (size_t)(a.out_row ? a.out_row[seg] : seg) * a.ld_out + col;
+        const int64_t orow = a.out_row ? a.out_row[seg] : seg;
+        if (a.csub_v) {
+          const float sc = a.csub_s ? a.csub_s[orow] : 1.f;
+          const float4 cv = *reinterpret_cast<const float4*>(a.csub_v + col);
+          t.x -= sc * cv.x;
+          t.y -= sc * cv.y;
+          t.z -= sc * cv.z;
+          t.w -= sc * cv.w;
+        }
+        const size_t o = (size_t)orow * a.ld_out + col;
         if (a.out_f32) *reinterpret_cast<float4*>(a.out_f32 + o) = t;
         if (a.out_bf16) {
           uint2 b;
@@ -349,7 +367,8 @@ __global__ __launch_bounds__(256) void spmm_merge4_kernel(SpmmArgs a) {
 __global__ __launch_bounds__(256) void spmm_fixup_kernel(const int32_t* part_seg, const int32_t* fix_w0,
                                                          int64_t nwaves, const float* carry, const float* head,
                                                          float* out_f32, uint16_t* out_bf16, int ld_out, int lp,
-                                                         const int32_t* out_row) {
+                                                         const int32_t* out_row, const float* csub_v,
+                                                         const float* csub_s) {
   const int lane = threadIdx.x & 63;
   const int64_t w1 = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (w1 >= nwaves) return;
@@ -367,7 +386,13 @@ __global__ __launch_bounds__(256) void spmm_fixup_kernel(const int32_t* part_seg
   const float2 h = *reinterpret_cast<const float2*>(head + (size_t)w1 * 128 + col);
   s.x += h.x;
   s.y += h.y;
-  const size_t o = (size_t)(out_row ? out_row[c] : c) * ld_out + col;
+  const int64_t orow = out_row ? out_row[c] : c;
+  if (csub_v) {
+    const float sc = csub_s ? csub_s[orow] : 1.f;
+    s.x -= sc * csub_v[col];
+    s.y -= sc * csub_v[col + 1];
+  }
+  const size_t o = (size_t)orow * ld_out + col;
   if (out_f32) store2_f32(out_f32, o, s);
   if (out_bf16) store2_bf16(out_bf16, o, s);
 }
@@ -375,10 +400,10 @@ __global__ __launch_bounds__(256) void spmm_fixup_kernel(const int32_t* part_seg
 }  // namespace
 
 void launch_spmm_main(const MergePlan& p, int lp, const void* in, bool in_bf16, int ld_in, float* out_f32,
-                      uint16_t* out_bf16, int ld_out, hipStream_t st) {
+                      uint16_t* out_bf16, int ld_out, hipStream_t st, SpmmCorr corr) {
   if (p.nwaves <= 0) return;
   SpmmArgs a{p.ptr, p.idx, p.val, p.part_seg, p.part_e, p.nseg, p.nwaves, in, ld_in, out_f32, out_bf16,
-             ld_out, lp, p.carry, p.head, p.sweep, p.out_row};
+             ld_out, lp, p.carry, p.head, p.sweep, p.out_row, corr.v, corr.s};
   unsigned grid = (unsigned)((p.nwaves + 3) / 4);
   if (p.sweep && grid > kSweepBlocks) grid = kSweepBlocks;
   // paired 16-byte gathers when every row of in and out starts 16-byte (FP32) or 8-byte
@@ -396,17 +421,18 @@ void launch_spmm_main(const MergePlan& p, int lp, const void* in, bool in_bf16, 
   else spmm_merge_kernel<false><<<grid, 256, 0, st>>>(a);
 }
 
-void launch_spmm_fixup(const MergePlan& p, int lp, float* out_f32, uint16_t* out_bf16, int ld_out, hipStream_t st) {
+void launch_spmm_fixup(const MergePlan& p, int lp, float* out_f32, uint16_t* out_bf16, int ld_out, hipStream_t st,
+                       SpmmCorr corr) {
   if (p.nwaves <= 0) return;
   const unsigned grid = (unsigned)((p.nwaves + 3) / 4);
   spmm_fixup_kernel<<<grid, 256, 0, st>>>(p.part_seg, p.fix_w0, p.nwaves, p.carry, p.head, out_f32, out_bf16,
-                                          ld_out, lp, p.out_row);
+                                          ld_out, lp, p.out_row, corr.v, corr.s);
 }
 
 void launch_spmm(const MergePlan& p, int lp, const void* in, bool in_bf16, int ld_in, float* out_f32,
-                 uint16_t* out_bf16, int ld_out, hipStream_t st) {
-  launch_spmm_main(p, lp, in, in_bf16, ld_in, out_f32, out_bf16, ld_out, st);
-  launch_spmm_fixup(p, lp, out_f32, out_bf16, ld_out, st);
+                 uint16_t* out_bf16, int ld_out, hipStream_t st, SpmmCorr corr) {
+  launch_spmm_main(p, lp, in, in_bf16, ld_in, out_f32, out_bf16, ld_out, st, corr);
+  launch_spmm_fixup(p, lp, out_f32, out_bf16, ld_out, st, corr);
 }
 
 }  // namespace frpca

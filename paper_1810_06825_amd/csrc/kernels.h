@@ -5,6 +5,13 @@
 
 namespace frpca {
 
+// Rank-1 term subtracted from every finished output row, out[r] -= s[r] v (the centred
+// products of k_center.hip); none when v is null, s = 1 when null.
+struct SpmmCorr {
+  const float* v = nullptr;  // [lp]
+  const float* s = nullptr;  // [output rows]
+};
+
 // ---------------------------------------------------------------- Gaussian test matrix
 // out[r*ld + j] = normal(seed, r*l + j) for j < l, 0 for l <= j < ld; FP32 and/or BF16.
 void launch_gaussian(uint64_t seed, int64_t rows, int l, int ld, float* out_f32,
@@ -55,7 +62,14 @@ void launch_rebase(const int32_t* ptr, int64_t count, int32_t base, int32_t* out
 // X[c] = sum over row blocks of the hot partial rows of c (fixed order), or the tail row of c.
 void launch_colmap_inverse(const int32_t* colmap, int64_t n, int32_t* hotcol, int32_t* tailcol, hipStream_t st);
 void launch_bcsc_combine(const float* P, int ldp, const int32_t* hotcol, int64_t hot_cols, int64_t nblk, int lp,
-                         float* X32, uint16_t* X16, int ldx, hipStream_t st);
+                         float* X32, uint16_t* X16, int ldx, hipStream_t st, SpmmCorr corr = {});
+// centred products (k_center.hip)
+void launch_colmean(const int32_t* cp, const float* val, int64_t n, int64_t m, float* mu, hipStream_t st);
+size_t wsum_temp_bytes(int64_t rows);
+void launch_wsum(const void* P, bool bf16, int ldp, int64_t rows, int lp, const float* w, double scale, double* part,
+                 float* v, hipStream_t st);
+void launch_center_corr(const float* a, const float* V, const float* b, const float* R, int64_t n, int k, float* corr,
+                        hipStream_t st);
 
 // ---------------------------------------------------------------- merge-path products
 struct MergePlan {
@@ -85,11 +99,11 @@ void launch_merge_fixplan(MergePlan& p, hipStream_t st);
 // launch_spmm_main writes every segment that ends inside one partition and the carries of
 // cut segments; launch_spmm_fixup then completes the cut segments. launch_spmm does both.
 void launch_spmm_main(const MergePlan& p, int lp, const void* in, bool in_bf16, int ld_in,
-                      float* out_f32, uint16_t* out_bf16, int ld_out, hipStream_t st);
+                      float* out_f32, uint16_t* out_bf16, int ld_out, hipStream_t st, SpmmCorr corr = {});
 void launch_spmm_fixup(const MergePlan& p, int lp, float* out_f32, uint16_t* out_bf16,
-                       int ld_out, hipStream_t st);
+                       int ld_out, hipStream_t st, SpmmCorr corr = {});
 void launch_spmm(const MergePlan& p, int lp, const void* in, bool in_bf16, int ld_in,
-                 float* out_f32, uint16_t* out_bf16, int ld_out, hipStream_t st);
+                 float* out_f32, uint16_t* out_bf16, int ld_out, hipStream_t st, SpmmCorr corr = {});
 
 // ---------------------------------------------------------------- dense kernels
 // Gram G = X1^T X2 (l x l, FP64, ld = ldg) of tall panels (rows x l); symmetric when
@@ -134,6 +148,7 @@ void launch_adjoint_small(const double* J, const double* K, const float* S, cons
                           int k, bool has_du, bool has_dv, double* CU, double* CV, double* SP,
                           hipStream_t st);
 void launch_sddmm(const int32_t* rp, const int32_t* col, int64_t m, int w, const float* P1,
-                  const float* Q1, const float* P2, const float* Q2, float* dval, hipStream_t st);
+                  const float* Q1, const float* P2, const float* Q2, float* dval, hipStream_t st,
+                  const float* corr = nullptr);
 
 }  // namespace frpca
