@@ -227,6 +227,14 @@ def main():
         extras["bf16_sigma_rel_diff_vs_fp32"] = float(np.max(np.abs(Sb.double().cpu().numpy() - Sf) / Sf))
         log(f"BF16 panels: {mb:.3f} ms, sigma rel diff vs FP32 {extras['bf16_sigma_rel_diff_vs_fp32']:.2e}")
         mat_b.close()
+        # centred PCA (A - 1 mu^T, never formed): cost of the rank-1 terms
+        mat_c = FrPCA.from_csr(A, device="cuda:0", center=True, timing=True)
+        mc, _ = timed_runs(mat_c, k, q, s, max(3, args.steps // 2), 1, torch)
+        cinf = mat_c.info()
+        extras["ms_centered"] = round(mc, 3)
+        extras["centered_terms_ms"] = round(cinf["t_ms"]["center"] / max(3, args.steps // 2), 4)
+        log(f"centred: {mc:.3f} ms (rank-1 terms {extras['centered_terms_ms']:.3f} ms)")
+        mat_c.close()
 
     cpu = None
     if not args.no_cpu_baseline:

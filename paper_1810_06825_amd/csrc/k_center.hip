@@ -24,28 +24,42 @@ __global__ __launch_bounds__(256) void colmean_kernel(const int32_t* cp, const f
   if (lane == 0) mu[c] = (float)(s / (double)m);
 }
 
-constexpr int kWsumRows = 2048;  // rows per block of the weighted column sums
+constexpr int kWsumBlocks = 512;  // blocks of the weighted column sums (each a stretch of rows)
 
-// Block partials of sum_r w[r] P[r, :] (w = 1 when null) in FP64: thread t takes column
-// t % 128 of the rows r0 + t / 128, r0 + t / 128 + 2, ...; the two row streams meet in LDS.
+// Block partials of sum_r w[r] P[r, :] (w = 1 when null) in FP64. A half-wave takes one row
+// (lane L covers columns 4 (L mod 32) .. + 3), so a block of 4 waves walks 8 rows at a time
+// through its stretch; the 8 row streams are added in a fixed order through LDS.
 template <bool BF16>
 __global__ __launch_bounds__(256) void wsum_partial_kernel(const void* P, int ldp, int64_t rows, int lp, const float* w,
                                                            double* part) {
-  __shared__ double sh[128];
-  const int t = threadIdx.x, col = t & 127, stream = t >> 7;
-  const int64_t r0 = (int64_t)blockIdx.x * kWsumRows;
-  const int64_t r1 = min(rows, r0 + kWsumRows);
-  double s = 0.0;
-  if (col < lp) {
-    for (int64_t r = r0 + stream; r < r1; r += 2) {
-      const double x = BF16 ? (double)bf16_to_f32(static_cast<const uint16_t*>(P)[(size_t)r * ldp + col])
-                            : (double)static_cast<const float*>(P)[(size_t)r * ldp + col];
-      s += w ? (double)w[r] * x : x;
+  __shared__ double sh[8][128];
+  const int t = threadIdx.x, stream = t >> 5, c0 = 4 * (t & 31);
+  const int64_t per = (rows + gridDim.x - 1) / gridDim.x;
+  const int64_t r0 = (int64_t)blockIdx.x * per;
+  const int64_t r1 = min(rows, r0 + per);
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int64_t r = r0 + stream; r < r1; r += 8) {
+    const double wr = w ? (double)w[r] : 1.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (c0 + q < lp) {
+        const size_t o = (size_t)r * ldp + c0 + q;
+        const double x = BF16 ? (double)bf16_to_f32(static_cast<const uint16_t*>(P)[o])
+                              : (double)static_cast<const float*>(P)[o];
+        s[q] += wr * x;
+      }
     }
   }
-  if (stream == 1) sh[col] = s;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) sh[stream][c0 + q] = s[q];
   __syncthreads();
-  if (stream == 0) part[(size_t)blockIdx.x * 128 + col] = s + sh[col];
+  if (t < 128) {
+    double tot = 0.0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) tot += sh[i][t];
+    part[(size_t)blockIdx.x * 128 + t] = tot;
+  }
 }
 
 // v[c] = scale * (sum of the block partials in block order)
@@ -54,6 +68,7 @@ __global__ __launch_bounds__(128) void wsum_final_kernel(const double* part, int
   const int c = threadIdx.x;
   if (c >= lp) return;
   double s = 0.0;
+#pragma unroll 8
   for (int64_t b = 0; b < nblk; ++b) s += part[(size_t)b * 128 + c];
   v[c] = (float)(scale * s);
 }
@@ -79,18 +94,18 @@ void launch_colmean(const int32_t* cp, const float* val, int64_t n, int64_t m, f
 }
 
 size_t wsum_temp_bytes(int64_t rows) {
-  const int64_t nblk = rows > kWsumRows ? (rows + kWsumRows - 1) / kWsumRows : 1;
-  return (size_t)nblk * 128 * sizeof(double);
+  (void)rows;
+  return (size_t)kWsumBlocks * 128 * sizeof(double);
 }
 
 void launch_wsum(const void* P, bool bf16, int ldp, int64_t rows, int lp, const float* w, double scale, double* part,
                  float* v, hipStream_t st) {
-  const int64_t nblk = rows > kWsumRows ? (rows + kWsumRows - 1) / kWsumRows : 1;
-  if (rows > 0) {
+  const int64_t nblk = rows < kWsumBlocks ? (rows > 0 ? rows : 0) : kWsumBlocks;
+  if (nblk > 0) {
     if (bf16) wsum_partial_kernel<true><<<(unsigned)nblk, 256, 0, st>>>(P, ldp, rows, lp, w, part);
     else wsum_partial_kernel<false><<<(unsigned)nblk, 256, 0, st>>>(P, ldp, rows, lp, w, part);
   }
-  wsum_final_kernel<<<1, 128, 0, st>>>(part, rows > 0 ? nblk : 0, lp, scale, v);
+  wsum_final_kernel<<<1, 128, 0, st>>>(part, nblk, lp, scale, v);
 }
 
 void launch_center_corr(const float* a, const float* V, const float* b, const float* R, int64_t n, int k, float* corr,
