@@ -103,6 +103,22 @@ def test_full_subspace_is_exact_svd():
     assert np.max(np.abs(Sg - sref) / sref) < 1e-4
 
 
+def test_maximum_sketch_width():
+    # l = k + s = 128, the widest sketch the library takes (panel rows of 128 floats)
+    A = zipf_lognormal(m=30_011, n=4_003, t=40)
+    r, *_ = check(A, 100, 5, 28, 4242)
+    assert r["ok"], r
+
+
+def test_sketch_wider_than_128_rejected():
+    A = random_sparse(400, 300, 0.05, seed=3)
+    mat = FrPCA.from_csr(A, device=DEV)
+    with pytest.raises(FrpcaError) as ei:
+        mat.run(100, 3, 29, 1)
+    assert ei.value.code == binding.FRPCA_EINVAL
+    mat.close()
+
+
 def test_bf16_panel_variant_error_stated():
     A = zipf_lognormal(m=30_011, n=4_003, t=40)
     say("bf16 panels")
