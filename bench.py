@@ -227,6 +227,19 @@ def main():
         extras["bf16_sigma_rel_diff_vs_fp32"] = float(np.max(np.abs(Sb.double().cpu().numpy() - Sf) / Sf))
         log(f"BF16 panels: {mb:.3f} ms, sigma rel diff vs FP32 {extras['bf16_sigma_rel_diff_vs_fp32']:.2e}")
         mat_b.close()
+        # eigSVD's Gram on the FP32 matrix cores (16-row FP32 sums added in FP64): time and
+        # singular-value difference against the default FP64-MFMA Gram
+        mat_g = FrPCA.from_csr(A, device="cuda:0", gram_f32=True, timing=True)
+        ng = max(3, args.steps // 2)
+        mg, (_, Sg32, _) = timed_runs(mat_g, k, q, s, ng, 1, torch)
+        ginf = mat_g.info()
+        extras["ms_gram_f32"] = round(mg, 3)
+        extras["gram_f32_gram_ms"] = round(ginf["t_ms"]["gram"] / ng, 4)
+        extras["gram_f32_sigma_rel_diff_vs_fp64_gram"] = float(
+            np.max(np.abs(Sg32.double().cpu().numpy() - Sf) / Sf))
+        log(f"FP32-MFMA Gram: {mg:.3f} ms (Gram {extras['gram_f32_gram_ms']:.3f} ms), sigma rel diff vs FP64 Gram "
+            f"{extras['gram_f32_sigma_rel_diff_vs_fp64_gram']:.2e}")
+        mat_g.close()
         # centred PCA (A - 1 mu^T, never formed): cost of the rank-1 terms
         mat_c = FrPCA.from_csr(A, device="cuda:0", center=True, timing=True)
         mc, _ = timed_runs(mat_c, k, q, s, max(3, args.steps // 2), 1, torch)
@@ -255,11 +268,17 @@ def main():
         sig_err = float(np.max(np.abs(Sg - So) / So))
         Qo = np.linalg.qr(Vo)[0]
         sin_v = float(np.linalg.norm(Vg - Qo @ (Qo.T @ Vg), 2))
+        ms_s = FrPCA.from_csr(As, device="cuda:0", gram_f32=True)
+        Sg32 = ms_s.run(k, q, s, SEED)[1].double().cpu().numpy()
+        ms_s.close()
+        sig_err32 = float(np.max(np.abs(Sg32 - So) / So))
         cpu = {"value": round(tcpu * scale, 2), "unit": "s", "cores": int(cores), "kind": "oracle",
                "sample": f"first {m_s} of {A.m} rows ({As.nnz} nnz), same k/s/q/seed; {tcpu:.1f} s measured, "
                          f"scaled by nnz ratio {scale:.2f}",
-               "gpu_vs_oracle_on_sample": {"sigma_rel_err": sig_err, "sin_theta_V": sin_v}}
-        log(f"oracle on sample: {tcpu:.1f} s -> {tcpu * scale:.1f} s scaled; GPU sigma err {sig_err:.2e}")
+               "gpu_vs_oracle_on_sample": {"sigma_rel_err": sig_err, "sin_theta_V": sin_v,
+                                           "sigma_rel_err_gram_f32": sig_err32}}
+        log(f"oracle on sample: {tcpu:.1f} s -> {tcpu * scale:.1f} s scaled; GPU sigma err {sig_err:.2e} "
+            f"(FP32-MFMA Gram {sig_err32:.2e})")
 
     out = {
         "metric": "frPCA wall time (s) + SpMM HBM GB/s at k=100; fwd+bwd time vs fwd at stated error",

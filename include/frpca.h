@@ -71,6 +71,12 @@ typedef struct {
                            means follow frpca_set_values; frpca_backward then returns the
                            gradient with respect to A's stored values through the
                            centring. 0 (default): A itself.                            */
+  int gram_f32;         /* 1: the Gram matrices of eigSVD (Alg. 2) use the FP32 matrix
+                           cores: FP32 partial sums over 16 rows, added in FP64. Relative
+                           error of sigma_k up to about 8 u32 (sigma_1/sigma_k)^2
+                           (u32 = 2^-24: half the 16-row sum times unit roundoff).
+                           0 (default): FP64 matrix cores on the FP32 panels, each product
+                           exact and only the FP64 sums rounded.                      */
 } frpca_opts;
 
 typedef struct {
@@ -172,7 +178,8 @@ int frpca_spmm(frpca_t h, int trans, int l, const void* in, int in_bf16, int ld_
                int out_bf16, int ld_out);
 
 /* Gram matrix of a tall panel (Alg. 2 step 1): G = X^T X, X: device float[rows*ldx]
- * (l columns), G: device double[l*l] row-major, accumulated in FP64 on MFMA. */
+ * (l columns), G: device double[l*l] row-major, accumulated in FP64 on MFMA (FP32 MFMA
+ * sums over 16 rows, added in FP64, when the handle was created with opts.gram_f32). */
 int frpca_gram(frpca_t h, int64_t rows, int l, const float* X, int ldx, double* G);
 
 /* Symmetric eigendecomposition (Alg. 2 step 2) in FP64 (Householder tridiagonalization,
@@ -183,7 +190,7 @@ int frpca_gram(frpca_t h, int64_t rows, int l, const float* X, int ldx, double* 
 int frpca_eig(frpca_t h, int l, const double* G, double* W, double* d);
 
 /* eigSVD basis (Alg. 2): Q = X V diag(1/S) with S ascending; S_j <= tol * max(S) gives a
- * zero column (tol <= 0 selects 1e-12). X, Q: device float panels (rows x l), S: device
+ * zero column (tol <= 0 selects 1e-12). The Gram follows opts.gram_f32 as frpca_gram. X, Q: device float panels (rows x l), S: device
  * double[l] (ascending, zeroed where dropped). */
 int frpca_eigsvd(frpca_t h, int64_t rows, int l, const float* X, int ldx, float* Q, int ldq,
                  double* S, double tol);

@@ -551,7 +551,7 @@ int frpca_run(frpca_t h, int k, int p_passes, int s_oversample, uint64_t seed, f
     auto gram_eig = [&](const float* P, int64_t rows) {
       {
         frpca_ctx::Scope t(h, FRPCA_T_GRAM);
-        launch_gram(P, false, LP, nullptr, 0, rows, l, h->gram_part, h->G, l, st);
+        launch_gram(P, false, LP, nullptr, 0, rows, l, h->gram_part, h->G, l, st, h->opts.gram_f32 != 0);
       }
       frpca_ctx::Scope t(h, FRPCA_T_EIG);
       launch_eig(h->G, l, l, h->d, h->W, h->eig_tmp, st);
@@ -770,7 +770,8 @@ int frpca_gram(frpca_t h, int64_t rows, int l, const float* X, int ldx, double* 
   return guarded(h, [&] {
     FRPCA_CHECK(rows >= 0 && l >= 1 && l <= kMaxL && ldx >= l && X && G, FRPCA_EINVAL, "bad Gram arguments");
     DeviceTemp part(gram_partial_bytes(l));
-    launch_gram(X, false, ldx, nullptr, 0, rows, l, static_cast<double*>(part.p), G, l, h->stream);
+    launch_gram(X, false, ldx, nullptr, 0, rows, l, static_cast<double*>(part.p), G, l, h->stream,
+                h->opts.gram_f32 != 0);
     check_launch();
     FRPCA_HIP(hipStreamSynchronize(h->stream));
   });
@@ -800,7 +801,7 @@ int frpca_eigsvd(frpca_t h, int64_t rows, int l, const float* X, int ldx, float*
     double* B = W + kMaxL * kMaxL;
     double* d = B + kMaxL * kMaxL;
     hipStream_t st = h->stream;
-    launch_gram(X, false, ldx, nullptr, 0, rows, l, static_cast<double*>(part.p), G, l, st);
+    launch_gram(X, false, ldx, nullptr, 0, rows, l, static_cast<double*>(part.p), G, l, st, h->opts.gram_f32 != 0);
     launch_eig(G, l, l, d, W, static_cast<double*>(etmp.p), st);
     launch_eigsvd_coeffs(d, W, l, l, tol, B, S, st);
     launch_tsmm(X, false, ldx, rows, l, B, l, l, l, Q, ldq, nullptr, 0, false, st);

@@ -17,11 +17,20 @@ namespace frpca {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// FP32 variant (F32, symmetric Gram only): v_mfma_f32_16x16x4f32 on the FP32 inputs, whose
+// partial sums over kFlushSteps row steps (16 rows per stream) are added into FP64 accumulators. Its 16 x 16
+// result holds value q of lane l at row 4 (l/16) + q (the FP64 instruction: row l/16 + 4q);
+// the partial tiles keep the layout of the instruction that made them and the reduction maps
+// each back.
+constexpr int kFlushSteps = 4;
 
 constexpr int kGramThreads = 512;  // 8 waves: 4 groups of tile pairs x 2 interleaved row streams
 constexpr int kGramMaxBlocks = 512;
 constexpr int kMaxPairs = 64;      // 8 x 8 tiles
-constexpr int kRedPart = 4;        // block-sum interleave of the reduction
+constexpr int kRedPart = 16;       // block-sum interleave of the reduction
+constexpr int kRedEnt = 256 / kRedPart;  // entries per reduction workgroup
 
 template <int B, int E, class F>
 __device__ __forceinline__ void static_for(F&& f) {
@@ -90,7 +99,7 @@ __device__ __forceinline__ void gram_load(const float* X, int ld, int64_t row, b
   }
 }
 
-template <int NT, bool SYM, int PG>
+template <int NT, bool SYM, int PG, bool F32>
 __device__ __forceinline__ void gram_wave(const float* X1, int ld1, const float* X2, int ld2, bool vec, int64_t r0,
                                           int64_t r1, int half, int l, double* out, double* lds) {
   constexpr int NP = npairs(NT, SYM);
@@ -98,8 +107,13 @@ __device__ __forceinline__ void gram_wave(const float* X1, int ld1, const float*
   const int lane = threadIdx.x & 63;
   const int kr = lane >> 4, cc = lane & 15;
   d4 acc[PPW > 0 ? PPW : 1];
+  f4 acc32[PPW > 0 ? PPW : 1];
 #pragma unroll
-  for (int q = 0; q < (PPW > 0 ? PPW : 1); ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int q = 0; q < (PPW > 0 ? PPW : 1); ++q) {
+    acc[q] = d4{0.0, 0.0, 0.0, 0.0};
+    acc32[q] = f4{0.f, 0.f, 0.f, 0.f};
+  }
+  int steps = 0;
   float na[NT], nb[NT];
   int64_t r = r0 + 4 * half;
   if (r < r1) {
@@ -108,10 +122,16 @@ __device__ __forceinline__ void gram_wave(const float* X1, int ld1, const float*
   }
   for (; r < r1; r += 8) {
     double a[NT], b[NT];
+    float a32[NT], b32[NT];
 #pragma unroll
     for (int I = 0; I < NT; ++I) {
-      a[I] = (double)na[I];
-      if constexpr (!SYM) b[I] = (double)nb[I];
+      if constexpr (F32) {
+        a32[I] = na[I];
+        if constexpr (!SYM) b32[I] = nb[I];
+      } else {
+        a[I] = (double)na[I];
+        if constexpr (!SYM) b[I] = (double)nb[I];
+      }
     }
     // the next step's rows load while this step's MFMAs run
     const int64_t rn = r + 8;
@@ -122,8 +142,29 @@ __device__ __forceinline__ void gram_wave(const float* X1, int ld1, const float*
     static_for<0, PPW>([&](auto qc) {
       constexpr int p = PG + 4 * decltype(qc)::value;
       constexpr int I = pair_i(NT, SYM, p), J = pair_j(NT, SYM, p);
-      if constexpr (SYM) acc[qc] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[I], a[J], acc[qc], 0, 0, 0);
-      else acc[qc] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[I], b[J], acc[qc], 0, 0, 0);
+      if constexpr (F32) {
+        if constexpr (SYM) acc32[qc] = __builtin_amdgcn_mfma_f32_16x16x4f32(a32[I], a32[J], acc32[qc], 0, 0, 0);
+        else acc32[qc] = __builtin_amdgcn_mfma_f32_16x16x4f32(a32[I], b32[J], acc32[qc], 0, 0, 0);
+      } else {
+        if constexpr (SYM) acc[qc] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[I], a[J], acc[qc], 0, 0, 0);
+        else acc[qc] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[I], b[J], acc[qc], 0, 0, 0);
+      }
+    });
+    if constexpr (F32) {
+      if (++steps == kFlushSteps) {
+        steps = 0;
+        static_for<0, PPW>([&](auto qc) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) acc[qc][e] += (double)acc32[qc][e];
+          acc32[qc] = f4{0.f, 0.f, 0.f, 0.f};
+        });
+      }
+    }
+  }
+  if constexpr (F32) {
+    static_for<0, PPW>([&](auto qc) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[qc][e] += (double)acc32[qc][e];
     });
   }
   // the two row streams combine in LDS (second stream first, fixed order)
@@ -150,7 +191,7 @@ __device__ __forceinline__ void gram_wave(const float* X1, int ld1, const float*
   }
 }
 
-template <int NT, bool SYM>
+template <int NT, bool SYM, bool F32>
 __global__ __launch_bounds__(kGramThreads) void gram_kernel(const float* X1, int ld1, const float* X2, int ld2,
                                                             int vec, int64_t rows, int l, int64_t rows_per_block,
                                                             double* partial) {
@@ -161,29 +202,34 @@ __global__ __launch_bounds__(kGramThreads) void gram_kernel(const float* X1, int
   double* out = partial + (size_t)blockIdx.x * NP * 256;
   const int w = threadIdx.x >> 6, half = w >> 2;
   switch (w & 3) {
-    case 0: gram_wave<NT, SYM, 0>(X1, ld1, X2, ld2, vec != 0, r0, r1, half, l, out, lds); break;
-    case 1: gram_wave<NT, SYM, 1>(X1, ld1, X2, ld2, vec != 0, r0, r1, half, l, out, lds); break;
-    case 2: gram_wave<NT, SYM, 2>(X1, ld1, X2, ld2, vec != 0, r0, r1, half, l, out, lds); break;
-    default: gram_wave<NT, SYM, 3>(X1, ld1, X2, ld2, vec != 0, r0, r1, half, l, out, lds); break;
+    case 0: gram_wave<NT, SYM, 0, F32>(X1, ld1, X2, ld2, vec != 0, r0, r1, half, l, out, lds); break;
+    case 1: gram_wave<NT, SYM, 1, F32>(X1, ld1, X2, ld2, vec != 0, r0, r1, half, l, out, lds); break;
+    case 2: gram_wave<NT, SYM, 2, F32>(X1, ld1, X2, ld2, vec != 0, r0, r1, half, l, out, lds); break;
+    default: gram_wave<NT, SYM, 3, F32>(X1, ld1, X2, ld2, vec != 0, r0, r1, half, l, out, lds); break;
   }
 }
 
-// Sum of the block partials: 64 consecutive entries per workgroup, four interleaved block
-// streams per entry (stream s adds blocks s, s+4, ... in order), combined in a fixed order;
-// then the entry goes to its place in G (tile columns mapped back, both triangles for SYM).
+// Sum of the block partials: kRedEnt consecutive entries per workgroup, kRedPart interleaved
+// block streams per entry (stream s adds blocks s, s + kRedPart, ... in order), combined in a
+// fixed order; then the entry goes to its place in G (tile columns mapped back, both
+// triangles for SYM).
 __global__ __launch_bounds__(256) void gram_reduce_kernel(const double* partial, int nblk, int nt, bool sym,
-                                                          int l, double* G, int ldg) {
-  __shared__ double red[kRedPart][64];
+                                                          bool f32_layout, int l, double* G, int ldg) {
+  __shared__ double red[kRedPart][kRedEnt];
   const int np = sym ? nt * (nt + 1) / 2 : nt * nt;
-  const int e = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int part = threadIdx.x >> 6;
+  const int x = threadIdx.x % kRedEnt, part = threadIdx.x / kRedEnt;
+  const int e = blockIdx.x * kRedEnt + x;
   double s = 0.0;
-  if (e < np * 256)
+  if (e < np * 256) {
+#pragma unroll 8
     for (int b = part; b < nblk; b += kRedPart) s += partial[(size_t)b * np * 256 + e];
-  red[part][threadIdx.x & 63] = s;
+  }
+  red[part][x] = s;
   __syncthreads();
   if (part != 0 || e >= np * 256) return;
-  s = (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
+  s = 0.0;
+#pragma unroll
+  for (int q = 0; q < kRedPart; ++q) s += red[q][x];
   const int p = e >> 8, t = e & 255, lane = t >> 2, r = t & 3;
   int I, J;
   if (sym) {
@@ -198,7 +244,7 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(const double* partial,
     I = p / nt;
     J = p % nt;
   }
-  const int i = gram_col(nt, I, (lane >> 4) + 4 * r);
+  const int i = gram_col(nt, I, f32_layout ? 4 * (lane >> 4) + r : (lane >> 4) + 4 * r);
   const int j = gram_col(nt, J, lane & 15);
   if (i >= l || j >= l) return;
   if (sym) {
@@ -210,14 +256,14 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(const double* partial,
   }
 }
 
-template <bool SYM>
+template <bool SYM, bool F32>
 void gram_dispatch(int nt, unsigned grid, const float* X1, int ld1, const float* X2, int ld2, int vec, int64_t rows,
                    int l, int64_t rpb, double* partial, hipStream_t st) {
   switch (nt) {
-    case 2: gram_kernel<2, SYM><<<grid, kGramThreads, 0, st>>>(X1, ld1, X2, ld2, vec, rows, l, rpb, partial); break;
-    case 4: gram_kernel<4, SYM><<<grid, kGramThreads, 0, st>>>(X1, ld1, X2, ld2, vec, rows, l, rpb, partial); break;
-    case 6: gram_kernel<6, SYM><<<grid, kGramThreads, 0, st>>>(X1, ld1, X2, ld2, vec, rows, l, rpb, partial); break;
-    default: gram_kernel<8, SYM><<<grid, kGramThreads, 0, st>>>(X1, ld1, X2, ld2, vec, rows, l, rpb, partial); break;
+    case 2: gram_kernel<2, SYM, F32><<<grid, kGramThreads, 0, st>>>(X1, ld1, X2, ld2, vec, rows, l, rpb, partial); break;
+    case 4: gram_kernel<4, SYM, F32><<<grid, kGramThreads, 0, st>>>(X1, ld1, X2, ld2, vec, rows, l, rpb, partial); break;
+    case 6: gram_kernel<6, SYM, F32><<<grid, kGramThreads, 0, st>>>(X1, ld1, X2, ld2, vec, rows, l, rpb, partial); break;
+    default: gram_kernel<8, SYM, F32><<<grid, kGramThreads, 0, st>>>(X1, ld1, X2, ld2, vec, rows, l, rpb, partial); break;
   }
 }
 
@@ -226,7 +272,7 @@ void gram_dispatch(int nt, unsigned grid, const float* X1, int ld1, const float*
 size_t gram_partial_bytes(int /*l*/) { return (size_t)kGramMaxBlocks * kMaxPairs * 256 * sizeof(double); }
 
 void launch_gram(const void* X1, bool /*bf16*/, int ld1, const float* X2, int ld2, int64_t rows, int l,
-                 double* partial, double* G, int ldg, hipStream_t st) {
+                 double* partial, double* G, int ldg, hipStream_t st, bool f32_mfma) {
   int nt = (l + 15) / 16;
   nt += nt & 1;
   const bool sym = (X2 == nullptr);
@@ -238,10 +284,13 @@ void launch_gram(const void* X1, bool /*bf16*/, int ld1, const float* X2, int ld
   if (grid < 1) grid = 1;
   int64_t rpb = (rows + grid - 1) / grid;
   rpb = (rpb + 7) / 8 * 8;
-  if (sym) gram_dispatch<true>(nt, (unsigned)grid, x1, ld1, x1, ld1, vec, rows, l, rpb, partial, st);
-  else gram_dispatch<false>(nt, (unsigned)grid, x1, ld1, X2, ld2, vec, rows, l, rpb, partial, st);
+  const bool f32 = f32_mfma && sym;  // the FP32 variant serves the symmetric Gram of eigSVD only
+  if (f32) gram_dispatch<true, true>(nt, (unsigned)grid, x1, ld1, x1, ld1, vec, rows, l, rpb, partial, st);
+  else if (sym) gram_dispatch<true, false>(nt, (unsigned)grid, x1, ld1, x1, ld1, vec, rows, l, rpb, partial, st);
+  else gram_dispatch<false, false>(nt, (unsigned)grid, x1, ld1, X2, ld2, vec, rows, l, rpb, partial, st);
   const int np = sym ? nt * (nt + 1) / 2 : nt * nt;
-  gram_reduce_kernel<<<(unsigned)((np * 256 + 63) / 64), 256, 0, st>>>(partial, (int)grid, nt, sym, l, G, ldg);
+  gram_reduce_kernel<<<(unsigned)((np * 256 + kRedEnt - 1) / kRedEnt), 256, 0, st>>>(partial, (int)grid, nt, sym, f32,
+                                                                                   l, G, ldg);
 }
 
 }  // namespace frpca

@@ -107,10 +107,11 @@ void launch_spmm(const MergePlan& p, int lp, const void* in, bool in_bf16, int l
 
 // ---------------------------------------------------------------- dense kernels
 // Gram G = X1^T X2 (l x l, FP64, ld = ldg) of tall panels (rows x l); symmetric when
-// X2 == nullptr (X2 = X1). partial: scratch of gram_partial_bytes().
+// X2 == nullptr (X2 = X1). partial: scratch of gram_partial_bytes(). f32_mfma (symmetric
+// Gram only): FP32 MFMA with FP32 partial sums over 16 rows, added in FP64 (default: FP64 MFMA).
 size_t gram_partial_bytes(int l);
 void launch_gram(const void* X1, bool bf16, int ld1, const float* X2, int ld2, int64_t rows,
-                 int l, double* partial, double* G, int ldg, hipStream_t st);
+                 int l, double* partial, double* G, int ldg, hipStream_t st, bool f32_mfma = false);
 // out[rows x c_out] = X[rows x kdim] B[kdim x c] (+ out if accumulate); columns c..c_out-1
 // written as 0. FP64 MFMA accumulation. out_bf16 (optional) receives a BF16 copy.
 void launch_tsmm(const void* X, bool x_bf16, int ldx, int64_t rows, int kdim, const double* B,

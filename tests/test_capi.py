@@ -43,6 +43,17 @@ def test_every_declared_symbol_is_exported(lib):
     assert sorted(binding.exported_symbols()) == names
 
 
+def test_options_struct_matches_header():
+    """The ctypes mirror of frpca_opts lists the header's fields in the header's order."""
+    from paper_1810_06825_amd import binding
+
+    text = open(HEADER).read()
+    body = re.search(r"typedef struct \{(.*?)\} frpca_opts;", text, re.S).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    fields = re.findall(r"^\s*(?:int|double|size_t)\s+(\w+);", body, re.M)
+    assert fields == [f[0] for f in binding.FrpcaOpts._fields_]
+
+
 def test_invalid_arguments_rejected_without_gpu(lib):
     from paper_1810_06825_amd import binding
 

@@ -127,6 +127,22 @@ def test_bf16_panel_variant_error_stated():
     assert r["sig_err"] < 1e-2
 
 
+@pytest.mark.parametrize("case", ["small_decay", "zipf_tall", "zipf_wide"])
+def test_gram_f32_variant_error_stated(case):
+    """eigSVD's Gram on the FP32 matrix cores (opts.gram_f32): its error against the FP64
+    oracle is reported. A CPU emulation of 16-row FP32 sums gives sigma errors of 2e-7 to
+    3.4e-5 and sines of 1e-5 to 6e-4 on these cases (the inner eigSVD of the power-iterated,
+    ill-conditioned panel contributes most); the bounds hold a margin of 30 on sigma."""
+    A, k, q, s, seed = {"small_decay": (small_decay(), 10, 3, 5, 20181015),
+                        "zipf_tall": (zipf_lognormal(m=30_011, n=4_003, t=40), 20, 5, 10, 77),
+                        "zipf_wide": (zipf_normal(m=3_001, n=20_011, t=30), 16, 5, 8, 99)}[case]
+    say("gram fp32", case)
+    r, *_ = check(A, k, q, s, seed, sig_tol=1.0, ang_tol=1.0, gram_f32=True)
+    say("  FP32-MFMA Gram error vs FP64 oracle:", r)
+    assert r["sig_err"] < 1e-3
+    assert r["sin_u"] < 1e-2 and r["sin_v"] < 1e-2
+
+
 def test_determinism_bitwise():
     A = zipf_lognormal(m=20_000, n=3_000, t=40)
     say("determinism")

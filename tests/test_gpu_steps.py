@@ -184,6 +184,33 @@ def test_gram_fp64_accumulation(l):
     assert np.array_equal(Gg, Gg.T)
 
 
+@pytest.mark.parametrize("l", [1, 15, 60, 128])
+def test_gram_fp32_mfma_variant(l):
+    """FP32 matrix-core Gram (opts.gram_f32): every FP32 partial sums 16 rows, so each entry is
+    within gamma_16 (here 2 * 16 u32, one rounding per product and per addition) of
+    sum_r |x_ri| |x_rj| of the exact FP64 value; a sum running longer in FP32, or a misplaced
+    output entry, breaks that bound."""
+    rows = 50_003
+    X = np.random.default_rng(100 + l).standard_normal((rows, l)).astype(np.float32)
+    ld = max(l, 4)
+    say("gram fp32 mfma", rows, l)
+    mat = _mat(random_sparse(8, 8, 0.5, seed=1), gram_f32=True)
+    Xd = torch.zeros((rows, ld), dtype=torch.float32)
+    Xd[:, :l] = torch.from_numpy(X)
+    Xd = Xd.to(DEV)
+    G = torch.zeros((l, l), dtype=torch.float64, device=DEV)
+    binding.frpca_gram(mat.h, rows, l, Xd, ld, G)
+    X64 = X.astype(np.float64)
+    ref = X64.T @ X64
+    absref = np.abs(X64).T @ np.abs(X64)
+    Gg = G.cpu().numpy()
+    err = np.abs(Gg - ref)
+    assert np.all(err <= 32 * 2.0 ** -24 * absref + 1e-13 * np.abs(ref).max())
+    assert np.array_equal(Gg, Gg.T)
+    # the FP32 sums did run: the FP64 path is exact to about 1e-15 relative
+    assert err.max() > 1e-10 * np.abs(ref).max()
+
+
 @pytest.mark.parametrize("l,kind", [(15, "spread"), (60, "spread"), (120, "spread"), (128, "cluster"),
                                     (7, "degenerate"), (2, "spread"), (1, "spread"), (3, "spread"),
                                     (128, "indefinite"), (100, "multiplicity"), (100, "psd_wide"),
