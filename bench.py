@@ -19,6 +19,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBPS = 8000.0       # MI355X HBM3E
 PEAK_FP64_TFLOPS = 78.6      # MI355X dense FP64 matrix
+PEAK_FP32_MFMA_TFLOPS = 157.3  # MI355X dense FP32 matrix
 SEED = 20181015
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic_spmm_zipf_lognormal.json")
 
@@ -36,6 +37,8 @@ def parse():
     p.add_argument("--passes", type=int, default=0, help="override q")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-extras", action="store_true", help="skip the odd/even, BF16 and backward timings")
+    p.add_argument("--gram-f32", action="store_true",
+                   help="time the variant whose eigSVD Gram runs on the FP32 matrix cores (profiling runs)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a 1 GiB elementwise read+write kernel 5 times (scales the HBM byte counters)")
     return p.parse_args()
@@ -119,7 +122,7 @@ def main():
     t0 = time.time()
     A = gen(**kw)
     log(f"generated {args.workload} {A.m}x{A.n} nnz={A.nnz} in {time.time() - t0:.1f}s")
-    mat = FrPCA.from_csr(A, device="cuda:0", timing=True)
+    mat = FrPCA.from_csr(A, device="cuda:0", timing=True, gram_f32=args.gram_f32)
     create_ms = mat.info()["create_ms"]
     log(f"create (validation + column-major mirror) {create_ms:.1f} ms")
 
@@ -185,12 +188,20 @@ def main():
         spmm_report["spmm_back"]["product_compulsory_GBps"] = round(spmm_bytes(A, l, trans=True) / (whole * 1e-3) / 1e9, 1)
     gram = None
     if "gram" in per:
-        # two Gram launches per run: the short-side panel of the one inner eigSVD basis and
-        # the long-side panel Z of the final step
+        # two Gram launches per run (the short-side panel of the one inner eigSVD basis and the
+        # long-side panel Z of the final step), each with its reduction. Algorithmic flops: the
+        # l (l + 1) / 2 distinct entries of the symmetric product, 2 per row each. Executed: the
+        # upper 16 x 16 tiles of l padded to an even tile count, as issued on the matrix cores.
         rows_total = min(A.m, A.n) + max(A.m, A.n)
-        flops = 2.0 * rows_total * l * l
-        tf = flops / (per["gram"]["ms_total_per_step"] * 1e-3) / 1e12
-        gram = {"tflops": round(tf, 2), "peak_fp64_mfma": PEAK_FP64_TFLOPS, "frac": round(tf / PEAK_FP64_TFLOPS, 4)}
+        nt = -(-l // 16)
+        nt += nt & 1
+        t_g = per["gram"]["ms_total_per_step"] * 1e-3
+        alg = rows_total * l * (l + 1) / t_g / 1e12
+        exe = 2.0 * rows_total * (nt * (nt + 1) // 2) * 256 / t_g / 1e12
+        peak = PEAK_FP32_MFMA_TFLOPS if args.gram_f32 else PEAK_FP64_TFLOPS
+        gram = {"mfma": "fp32" if args.gram_f32 else "fp64", "ms_per_run": round(t_g * 1e3, 4),
+                "algorithmic_tflops": round(alg, 2), "executed_tflops": round(exe, 2), "peak_tflops": peak,
+                "frac_algorithmic": round(alg / peak, 4), "frac_executed": round(exe / peak, 4)}
 
     extras = {}
     if not args.no_extras:
@@ -294,7 +305,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{args.workload} {A.m}x{A.n} CSR, {A.nnz} nnz", "m": A.m, "n": A.n,
-                   "nnz": A.nnz, "k": k, "s": s, "passes": q, "seed": SEED},
+                   "nnz": A.nnz, "k": k, "s": s, "passes": q, "seed": SEED,
+                   "gram": "fp32-mfma" if args.gram_f32 else "fp64-mfma"},
         "roofline": roof,
         "cpu_baseline": cpu,
         "spmm": spmm_report,
