@@ -186,7 +186,7 @@ int frpca_gram(frpca_t h, int64_t rows, int l, const float* X, int ldx, double* 
  * then bisection and twisted factorizations on a positive definite L D L^T representation):
  * G (device double[l*l], symmetric) = W diag(d) W^T with d ascending (device double[l])
  * and orthonormal W (device double[l*l] row-major, column j pairs with d[j]). l <= 128.
- * Allocates and frees a 256 KiB device scratch buffer per call. */
+ * Allocates and frees a device scratch buffer of about 266 KiB per call. */
 int frpca_eig(frpca_t h, int l, const double* G, double* W, double* d);
 
 /* eigSVD basis (Alg. 2): Q = X V diag(1/S) with S ascending; S_j <= tol * max(S) gives a

@@ -1,7 +1,8 @@
-// Symmetric eigendecomposition of the l x l Gram matrix (Alg. 2 step 2), FP64, one workgroup
-// of 16 waves. Householder tridiagonalization, then eigenpairs of the tridiagonal T by the
-// multiple relatively robust representations idea (Dhillon & Parlett, 2004), then the
-// back-transformation:
+// Symmetric eigendecomposition of the l x l Gram matrix (Alg. 2 step 2), FP64, in three
+// kernels: phases 1-2 and phases 4-5 each on one workgroup of 16 waves, phase 3 on one wave per
+// eigenvalue across the chip. Householder tridiagonalization, then eigenpairs of the
+// tridiagonal T by the multiple relatively robust representations idea (Dhillon & Parlett,
+// 2004), then the back-transformation:
 //
 //  1. Q^T G Q = T by Householder reflectors H_k = I - tau_k v_k v_k^T, v_k(0) = 1 (Golub &
 //     Van Loan, Alg. 8.3.1). G lives in registers as 4 x 4 tiles (thread t holds rows
@@ -18,8 +19,8 @@
 //     eigenvalues to high relative accuracy, so eigenvectors of eigenvalues with a relative
 //     gap of 1e-3 or more come out numerically orthogonal without any reorthogonalization.
 //  3. Eigenvalues mu of L D L^T by multisection on negative-pivot counts of the stationary
-//     qd transform L D L^T - x I = L+ D+ L+^T (four lanes per eigenvalue, five subintervals
-//     per step, geometric points while the bracket spans a wide ratio, reciprocals by the
+//     qd transform L D L^T - x I = L+ D+ L+^T (a wave per eigenvalue, 65 subintervals per
+//     step, geometric points while the bracket spans a wide ratio, reciprocals by the
 //     hardware estimate and two Newton steps), to a relative width of 4 eps.
 //  4. Each isolated eigenvector from the twisted factorization of L D L^T - mu I at the index
 //     r where |gamma_r| = |s_r + p_r + mu| is smallest (stationary and progressive qd
@@ -162,21 +163,44 @@ __device__ __forceinline__ double jitter(int g, int i) {
   return (double)h * (2.0 / 4294967296.0) - 1.0;
 }
 
-__global__ __launch_bounds__(kT) void syev_kernel(const double* G, int ldg, int n, double* d_out, double* W,
-                                                  double* scratch) {
-  __shared__ double A[kMaxL * kS];  // G, then the eigenvectors Z of T
+// The three kernels of one decomposition hand over through global scratch: the reflectors,
+// the cluster solves' L+ columns, then these arrays (written by the first kernel, mu by the
+// second).
+struct EigState {
+  double *d, *tau, *Dr, *Lr, *LLD, *bsig, *bgu, *btn, *mu, *misc;
+  int *bstart, *bsize;
+};
+constexpr size_t kStateDoubles = 9 * kMaxL + 8;
+__device__ __forceinline__ EigState eig_state(double* scratch) {
+  double* b = scratch + 2 * kMaxL * kMaxL;
+  EigState st;
+  st.d = b;
+  st.tau = b + kMaxL;
+  st.Dr = b + 2 * kMaxL;
+  st.Lr = b + 3 * kMaxL;
+  st.LLD = b + 4 * kMaxL;
+  st.bsig = b + 5 * kMaxL;
+  st.bgu = b + 6 * kMaxL;
+  st.btn = b + 7 * kMaxL;
+  st.mu = b + 8 * kMaxL;
+  st.misc = b + 9 * kMaxL;  // [0]: pivmin
+  st.bstart = reinterpret_cast<int*>(b + kStateDoubles);
+  st.bsize = st.bstart + kMaxL;
+  return st;
+}
+
+// Phases 1 and 2.
+__global__ __launch_bounds__(kT) void syev_tridiag_kernel(const double* G, int ldg, int n, double* scratch) {
+  __shared__ double A[kMaxL * kS];  // rows hold the reflectors v_k during the phase
   __shared__ double d[kMaxL], e[kMaxL], e2[kMaxL], tau[kMaxL], pw[kMaxL];
-  __shared__ double Dr[kMaxL], Lr[kMaxL], LLD[kMaxL], mu[kMaxL], shift[kMaxL];
+  __shared__ double Dr[kMaxL], Lr[kMaxL], LLD[kMaxL];
   __shared__ double bsig[kMaxL], bgl[kMaxL], bgu[kMaxL], btn[kMaxL];
   __shared__ double red[kT / 64], red2[kT / 64];
   __shared__ double colbuf[kMaxL];
-  __shared__ int bstart[kMaxL], bsize[kMaxL], bbad[kMaxL], cl0[kMaxL], incl[kMaxL], rank_s[kMaxL];
-  __shared__ int gs_list[kMaxL], slot_s[kMaxL];
-  __shared__ double lds_lp[kLdsSlots * kMaxL];
+  __shared__ int bstart[kMaxL], bsize[kMaxL], bbad[kMaxL];
   __shared__ int sh_int[4];
   __shared__ double sh_dbl[4];
   double* house = scratch;                   // kMaxL x kMaxL reflectors
-  double* lwork = scratch + kMaxL * kMaxL;   // per-column L+ of the cluster solves
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
   // ---------------------------------------------------------------- 1. tridiagonalization
@@ -430,53 +454,99 @@ __global__ __launch_bounds__(kT) void syev_kernel(const double* G, int ldg, int 
     __syncthreads();
   }
 
-  // ---------------------------------------------------------------- 3. eigenvalues of L D L^T
-  // Four lanes per eigenvalue (five subintervals per step) on the first eight waves: the
-  // counts are bound by FP64 issue, and this split balances the work against the latency of
-  // each lane's serial chain.
-  {
-    const int g = tid >> 2, sub = tid & 3;
-    const bool act = g < n && bsize[g] > 1;
-    int o = 0, nb = 1, want = 0;
-    double lo = 0.0, hi = 0.0;
-    if (act) {
-      o = bstart[g];
-      nb = bsize[g];
-      want = g - o;
-      hi = (bgu[o] - bsig[o]) + 4.0 * nb * kEps * fmax(btn[o], fabs(bsig[o])) + pivmin;
-    }
-    for (int it = 0; it < 96; ++it) {
-      const bool busy = act && !(lo > 0.0 && hi - lo <= 4.0 * kEps * hi);
-      if (!__any(busy)) break;  // per wave; the four lanes of a group agree on busy
-      double x;
-      if (lo == 0.0) {
-        x = ldexp(hi, -14 * (4 - sub));
-      } else if (hi > 1.5 * lo) {
-        x = lo * exp2(log2(hi / lo) * (double)(sub + 1) / 5.0);
-      } else {
-        x = lo + (hi - lo) * (double)(sub + 1) / 5.0;
-      }
-      x = fmin(fmax(x, lo), hi);
-      const int c = busy ? negcount(Dr, LLD, o, nb, x, pivmin) : 0;
-      int b = 4;
-      double xb = hi, xb1 = lo;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int cs = __shfl(c, (lane & ~3) + q);
-        const double xs = __shfl(x, (lane & ~3) + q);
-        if (b == 4 && cs > want) {
-          b = q;
-          xb = xs;
-        }
-        if (b == 4) xb1 = xs;
-      }
-      if (busy) {
-        lo = xb1;
-        hi = xb;
-      }
-    }
-    if (sub == 0 && g < n) mu[g] = act ? 0.5 * (lo + hi) : 0.0;
+  // hand-over to the eigenvalue and eigenvector kernels
+  const EigState st = eig_state(scratch);
+  for (int j = tid; j < n; j += kT) {
+    st.d[j] = d[j];
+    st.tau[j] = tau[j];
+    st.Dr[j] = Dr[j];
+    st.Lr[j] = Lr[j];
+    st.LLD[j] = LLD[j];
+    st.bsig[j] = bsig[j];
+    st.bgu[j] = bgu[j];
+    st.btn[j] = btn[j];
+    st.bstart[j] = bstart[j];
+    st.bsize[j] = bsize[j];
   }
+  if (tid == 0) st.misc[0] = pivmin;
+}
+
+// Phase 3: one wave per eigenvalue, multisection over 65 subintervals per step (lane i takes
+// the (i+1)-th point; geometric points while the bracket spans a wide ratio, or powers of two
+// below hi while its lower end is still 0), down to a relative width of 4 eps. Each lane runs
+// one negative-pivot count, a serial chain of n steps, so a step of the search costs one
+// chain; the waves of all eigenvalues run on separate SIMDs.
+constexpr int kBisWaves = 4;
+__global__ __launch_bounds__(64 * kBisWaves) void syev_bisect_kernel(int n, double* scratch) {
+  __shared__ double Ds[kMaxL], Ls[kMaxL];
+  const EigState st = eig_state(scratch);
+  for (int j = threadIdx.x; j < n; j += 64 * kBisWaves) {
+    Ds[j] = st.Dr[j];
+    Ls[j] = st.LLD[j];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int g = blockIdx.x * kBisWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (g >= n) return;
+  const int o = st.bstart[g], nb = st.bsize[g];
+  if (nb <= 1) {
+    if (lane == 0) st.mu[g] = 0.0;
+    return;
+  }
+  const double pivmin = st.misc[0];
+  const int want = g - o;
+  double lo = 0.0;
+  double hi = (st.bgu[o] - st.bsig[o]) + 4.0 * nb * kEps * fmax(st.btn[o], fabs(st.bsig[o])) + pivmin;
+  for (int it = 0; it < 64; ++it) {
+    if (lo > 0.0 && hi - lo <= 4.0 * kEps * hi) break;  // same on every lane
+    double x;
+    if (lo == 0.0) {
+      x = ldexp(hi, lane - 64);
+    } else if (hi > 1.5 * lo) {
+      x = lo * exp2(log2(hi / lo) * (double)(lane + 1) / 65.0);
+    } else {
+      x = lo + (hi - lo) * (double)(lane + 1) / 65.0;
+    }
+    x = fmin(fmax(x, lo), hi);
+    const int c = negcount(Ds, Ls, o, nb, x, pivmin);
+    // counts rise with x: the first lane whose count passes `want` closes the bracket
+    const uint64_t above = __ballot(c > want);
+    const int b = above ? __ffsll((unsigned long long)above) - 1 : 64;
+    const double nhi = b < 64 ? readlane_d(x, b) : hi;
+    const double nlo = b > 0 ? readlane_d(x, b - 1) : lo;
+    lo = nlo;
+    hi = nhi;
+  }
+  if (lane == 0) st.mu[g] = 0.5 * (lo + hi);
+}
+
+// Phases 4 and 5.
+__global__ __launch_bounds__(kT) void syev_vectors_kernel(int n, double* d_out, double* W, double* scratch) {
+  __shared__ double A[kMaxL * kS];  // the eigenvectors Z of T, then the reflectors
+  __shared__ double d[kMaxL], tau[kMaxL], pw[kMaxL];
+  __shared__ double Dr[kMaxL], Lr[kMaxL], LLD[kMaxL], mu[kMaxL], shift[kMaxL];
+  __shared__ double bsig[kMaxL];
+  __shared__ double red[kT / 64];
+  __shared__ int bstart[kMaxL], bsize[kMaxL], cl0[kMaxL], incl[kMaxL], rank_s[kMaxL];
+  __shared__ int gs_list[kMaxL], slot_s[kMaxL];
+  __shared__ double lds_lp[kLdsSlots * kMaxL];
+  __shared__ int sh_int[4];
+  double* house = scratch;                   // kMaxL x kMaxL reflectors
+  double* lwork = scratch + kMaxL * kMaxL;   // per-column L+ of the cluster solves
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const EigState st = eig_state(scratch);
+  for (int j = tid; j < n; j += kT) {
+    d[j] = st.d[j];
+    tau[j] = st.tau[j];
+    Dr[j] = st.Dr[j];
+    Lr[j] = st.Lr[j];
+    LLD[j] = st.LLD[j];
+    mu[j] = st.mu[j];
+    bsig[j] = st.bsig[j];
+    bstart[j] = st.bstart[j];
+    bsize[j] = st.bsize[j];
+  }
+  const double pivmin = st.misc[0];
   __syncthreads();
 
   // ---------------------------------------------------------------- 4. eigenvectors of T
@@ -729,10 +799,14 @@ __global__ __launch_bounds__(kT) void syev_kernel(const double* G, int ldg, int 
 
 }  // namespace
 
-size_t eig_scratch_bytes() { return 2 * (size_t)kMaxL * kMaxL * sizeof(double); }
+size_t eig_scratch_bytes() {
+  return (2 * (size_t)kMaxL * kMaxL + kStateDoubles) * sizeof(double) + 2 * (size_t)kMaxL * sizeof(int);
+}
 
 void launch_eig(const double* G, int ldg, int l, double* d, double* W, double* scratch, hipStream_t st) {
-  syev_kernel<<<1, kT, 0, st>>>(G, ldg, l, d, W, scratch);
+  syev_tridiag_kernel<<<1, kT, 0, st>>>(G, ldg, l, scratch);
+  syev_bisect_kernel<<<(unsigned)((l + kBisWaves - 1) / kBisWaves), 64 * kBisWaves, 0, st>>>(l, scratch);
+  syev_vectors_kernel<<<1, kT, 0, st>>>(l, d, W, scratch);
 }
 
 }  // namespace frpca

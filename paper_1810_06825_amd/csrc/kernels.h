@@ -119,8 +119,8 @@ void launch_tsmm(const void* X, bool x_bf16, int ldx, int64_t rows, int kdim, co
                  bool accumulate, hipStream_t st);
 
 // Symmetric eigendecomposition (G: l x l FP64, ldg): Householder tridiagonalization, then
-// relatively robust representations. d ascending, W l x l row-major (column j pairs with
-// d[j]); scratch holds eig_scratch_bytes() of device memory.
+// relatively robust representations (three launches). d ascending, W l x l row-major
+// (column j pairs with d[j]); scratch holds eig_scratch_bytes() of device memory.
 size_t eig_scratch_bytes();
 void launch_eig(const double* G, int ldg, int l, double* d, double* W, double* scratch, hipStream_t st);
 // eigSVD basis coefficients: B[a][j] = W[a][j] / sigma_j (0 if sigma_j <= tol*max), sigma out.
