@@ -7,8 +7,11 @@
 // B operand; the 16x16 result tile is held 4 values per lane: value q of lane l is row
 // l/16 + 4q, column l%16 (layout checked on gfx950). The l x l output is covered by NT x NT tiles (NT = ceil(l/16) rounded to even);
 // for the symmetric Gram only the NT(NT+1)/2 upper tiles are computed. The four waves of a
-// block split the tiles and walk the same rows 4 at a time. Each block writes its partial
-// tiles; a second kernel adds the partials of all blocks in block order (deterministic).
+// block split the tiles and walk the same rows 4 at a time. On panels padded to 16 NT columns
+// each wave keeps three row steps in flight in a ring of registers (unconditional loads, so the
+// compiler waits for each buffer's own loads); the row loads, not the matrix cores, bound the
+// one-step form. Each block writes its partial tiles; a second kernel adds the partials of all
+// blocks in block order (deterministic).
 #include <type_traits>
 
 #include "kernels.h"
@@ -99,8 +102,37 @@ __device__ __forceinline__ void gram_load(const float* X, int ld, int64_t row, b
   }
 }
 
+#ifndef FRPCA_GRAM_RING
+#define FRPCA_GRAM_RING 3
+#endif
+constexpr int kGramRing = FRPCA_GRAM_RING;  // row buffers per wave on the padded-panel path (0: off)
+
+// Unconditional load of one row for panels whose leading dimension covers every tile column
+// (ld >= 16 NT, 16-byte aligned rows); rows past r1 read row r1 - 1 (such loads only fill the
+// pipeline past the last step and are never used). Columns past l come from the padding: a
+// column only enters the Gram entries of its own row and column, which the reduction drops.
+template <int NT>
+__device__ __forceinline__ void gram_load_wide(const float* X, int ld, int64_t row, int64_t r1, int cc,
+                                               float v[NT]) {
+  constexpr int G4 = NT / 4;
+  const float* p = X + (size_t)(row < r1 ? row : r1 - 1) * ld;
+#pragma unroll
+  for (int g = 0; g < G4; ++g) {
+    const float4 w = *reinterpret_cast<const float4*>(p + 64 * g + 4 * cc);
+    v[4 * g] = w.x;
+    v[4 * g + 1] = w.y;
+    v[4 * g + 2] = w.z;
+    v[4 * g + 3] = w.w;
+  }
+  if constexpr (NT % 4 != 0) {
+    const float2 w = *reinterpret_cast<const float2*>(p + 64 * G4 + 2 * cc);
+    v[4 * G4] = w.x;
+    v[4 * G4 + 1] = w.y;
+  }
+}
+
 template <int NT, bool SYM, int PG, bool F32>
-__device__ __forceinline__ void gram_wave(const float* X1, int ld1, const float* X2, int ld2, bool vec, int64_t r0,
+__device__ __forceinline__ void gram_wave(const float* X1, int ld1, const float* X2, int ld2, int vec, int64_t r0,
                                           int64_t r1, int half, int l, double* out, double* lds) {
   constexpr int NP = npairs(NT, SYM);
   constexpr int PPW = (NP - PG + 3) / 4;  // pairs p = PG + 4q
@@ -114,30 +146,19 @@ __device__ __forceinline__ void gram_wave(const float* X1, int ld1, const float*
     acc32[q] = f4{0.f, 0.f, 0.f, 0.f};
   }
   int steps = 0;
-  float na[NT], nb[NT];
-  int64_t r = r0 + 4 * half;
-  if (r < r1) {
-    gram_load<NT>(X1, ld1, r + kr, r + kr < r1, l, cc, vec, na);
-    if constexpr (!SYM) gram_load<NT>(X2, ld2, r + kr, r + kr < r1, l, cc, vec, nb);
-  }
-  for (; r < r1; r += 8) {
+  // one step: the 4 rows in xa (and xb) enter every tile pair of this wave
+  auto step = [&](const float* xa, const float* xb) {
     double a[NT], b[NT];
     float a32[NT], b32[NT];
 #pragma unroll
     for (int I = 0; I < NT; ++I) {
       if constexpr (F32) {
-        a32[I] = na[I];
-        if constexpr (!SYM) b32[I] = nb[I];
+        a32[I] = xa[I];
+        if constexpr (!SYM) b32[I] = xb[I];
       } else {
-        a[I] = (double)na[I];
-        if constexpr (!SYM) b[I] = (double)nb[I];
+        a[I] = (double)xa[I];
+        if constexpr (!SYM) b[I] = (double)xb[I];
       }
-    }
-    // the next step's rows load while this step's MFMAs run
-    const int64_t rn = r + 8;
-    if (rn < r1) {
-      gram_load<NT>(X1, ld1, rn + kr, rn + kr < r1, l, cc, vec, na);
-      if constexpr (!SYM) gram_load<NT>(X2, ld2, rn + kr, rn + kr < r1, l, cc, vec, nb);
     }
     static_for<0, PPW>([&](auto qc) {
       constexpr int p = PG + 4 * decltype(qc)::value;
@@ -159,6 +180,49 @@ __device__ __forceinline__ void gram_wave(const float* X1, int ld1, const float*
           acc32[qc] = f4{0.f, 0.f, 0.f, 0.f};
         });
       }
+    }
+  };
+  int64_t r = r0 + 4 * half;
+  if (kGramRing > 0 && vec == 2 && r1 > r0 && ((r1 - r0) & 7) == 0) {
+    // every step of the stretch is full: a ring of kGramRing row buffers, each refilled
+    // kGramRing - 1 steps before its step, with a wave-uniform step count
+    constexpr int D = kGramRing > 0 ? kGramRing : 1;
+    float ra[D][NT], rb[D][NT];
+    const int64_t nsteps = (r1 - r0) / 8;
+    static_for<0, D - 1>([&](auto uc) {
+      constexpr int u = decltype(uc)::value;
+      gram_load_wide<NT>(X1, ld1, r + 8 * u + kr, r1, cc, ra[u]);
+      if constexpr (!SYM) gram_load_wide<NT>(X2, ld2, r + 8 * u + kr, r1, cc, rb[u]);
+    });
+    for (int64_t i = 0; i < nsteps; i += D) {
+      static_for<0, D>([&](auto uc) {
+        constexpr int u = decltype(uc)::value;
+        constexpr int un = (u + D - 1) % D;
+        const int64_t rn = r + 8 * (i + u + D - 1) + kr;
+        gram_load_wide<NT>(X1, ld1, rn, r1, cc, ra[un]);
+        if constexpr (!SYM) gram_load_wide<NT>(X2, ld2, rn, r1, cc, rb[un]);
+        if (i + u < nsteps) step(ra[u], rb[u]);
+      });
+    }
+  } else {
+    float na[NT], nb[NT], ca[NT], cb[NT];
+    if (r < r1) {
+      gram_load<NT>(X1, ld1, r + kr, r + kr < r1, l, cc, vec != 0, na);
+      if constexpr (!SYM) gram_load<NT>(X2, ld2, r + kr, r + kr < r1, l, cc, vec != 0, nb);
+    }
+    for (; r < r1; r += 8) {
+#pragma unroll
+      for (int I = 0; I < NT; ++I) {
+        ca[I] = na[I];
+        if constexpr (!SYM) cb[I] = nb[I];
+      }
+      // the next step's rows load while this step's MFMAs run
+      const int64_t rn = r + 8;
+      if (rn < r1) {
+        gram_load<NT>(X1, ld1, rn + kr, rn + kr < r1, l, cc, vec != 0, na);
+        if constexpr (!SYM) gram_load<NT>(X2, ld2, rn + kr, rn + kr < r1, l, cc, vec != 0, nb);
+      }
+      step(ca, cb);
     }
   }
   if constexpr (F32) {
@@ -200,12 +264,13 @@ __global__ __launch_bounds__(kGramThreads) void gram_kernel(const float* X1, int
   const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
   const int64_t r1 = min(rows, r0 + rows_per_block);
   double* out = partial + (size_t)blockIdx.x * NP * 256;
-  const int w = threadIdx.x >> 6, half = w >> 2;
+  // the wave index as a scalar: the row loops and the tile-group switch branch uniformly
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), half = w >> 2;
   switch (w & 3) {
-    case 0: gram_wave<NT, SYM, 0, F32>(X1, ld1, X2, ld2, vec != 0, r0, r1, half, l, out, lds); break;
-    case 1: gram_wave<NT, SYM, 1, F32>(X1, ld1, X2, ld2, vec != 0, r0, r1, half, l, out, lds); break;
-    case 2: gram_wave<NT, SYM, 2, F32>(X1, ld1, X2, ld2, vec != 0, r0, r1, half, l, out, lds); break;
-    default: gram_wave<NT, SYM, 3, F32>(X1, ld1, X2, ld2, vec != 0, r0, r1, half, l, out, lds); break;
+    case 0: gram_wave<NT, SYM, 0, F32>(X1, ld1, X2, ld2, vec, r0, r1, half, l, out, lds); break;
+    case 1: gram_wave<NT, SYM, 1, F32>(X1, ld1, X2, ld2, vec, r0, r1, half, l, out, lds); break;
+    case 2: gram_wave<NT, SYM, 2, F32>(X1, ld1, X2, ld2, vec, r0, r1, half, l, out, lds); break;
+    default: gram_wave<NT, SYM, 3, F32>(X1, ld1, X2, ld2, vec, r0, r1, half, l, out, lds); break;
   }
 }
 
@@ -278,7 +343,10 @@ void launch_gram(const void* X1, bool /*bf16*/, int ld1, const float* X2, int ld
   const bool sym = (X2 == nullptr);
   const float* x1 = static_cast<const float*>(X1);
   auto aligned = [](const float* x, int ld) { return (ld % 4) == 0 && (reinterpret_cast<uintptr_t>(x) % 16) == 0; };
-  const int vec = aligned(x1, ld1) && (sym || aligned(X2, ld2));
+  // 2: aligned rows whose leading dimension covers every tile column; 1: aligned rows;
+  // 0: element loads
+  int vec = aligned(x1, ld1) && (sym || aligned(X2, ld2)) ? 1 : 0;
+  if (vec && ld1 >= 16 * nt && (sym || ld2 >= 16 * nt)) vec = 2;
   int64_t grid = (rows + 127) / 128;
   if (grid > kGramMaxBlocks) grid = kGramMaxBlocks;
   if (grid < 1) grid = 1;

@@ -184,6 +184,28 @@ def test_gram_fp64_accumulation(l):
     assert np.array_equal(Gg, Gg.T)
 
 
+@pytest.mark.parametrize("f32", [False, True])
+def test_gram_padded_panel_padding_not_used(f32):
+    """Panels padded to a multiple of 32 columns take the unmasked-load path: the padding
+    (here NaN) may enter only Gram entries outside l x l, which are dropped. Rows cover full
+    8-row stretches in all blocks but the last, which keeps the masked path."""
+    rows, l, ld = 100_001, 120, 128
+    X = np.random.default_rng(31).standard_normal((rows, l)).astype(np.float32)
+    say("gram padded NaN", rows, l, ld, "f32" if f32 else "f64")
+    mat = _mat(random_sparse(8, 8, 0.5, seed=1), gram_f32=f32)
+    Xd = torch.full((rows, ld), float("nan"), dtype=torch.float32)
+    Xd[:, :l] = torch.from_numpy(X)
+    Xd = Xd.to(DEV)
+    G = torch.zeros((l, l), dtype=torch.float64, device=DEV)
+    binding.frpca_gram(mat.h, rows, l, Xd, ld, G)
+    X64 = X.astype(np.float64)
+    ref = X64.T @ X64
+    Gg = G.cpu().numpy()
+    assert np.all(np.isfinite(Gg))
+    bound = (32 * 2.0 ** -24 if f32 else 1e-13) * (np.abs(X64).T @ np.abs(X64)) + 1e-13 * np.abs(ref).max()
+    assert np.all(np.abs(Gg - ref) <= bound)
+
+
 @pytest.mark.parametrize("l", [1, 15, 60, 128])
 def test_gram_fp32_mfma_variant(l):
     """FP32 matrix-core Gram (opts.gram_f32): every FP32 partial sums 16 rows, so each entry is
