@@ -159,7 +159,8 @@ def main():
             # the SpMM source they were taken on
             with open(PROFILE_TRAFFIC) as f:
                 tr = json.load(f)
-            if tr.get("kernel_source_sha256") == spmm_source_hash() and dom in tr.get("per_launch", {}):
+            if (tr.get("kernel_source_sha256") == spmm_source_hash() and dom in tr.get("per_launch", {})
+                    and tr.get("workload", "").startswith(args.workload + " ")):
                 traffic = tr["per_launch"][dom]["hbm_bytes"]
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                 "frac": round(ach / PEAK_HBM_GBPS, 4), "traffic": traffic,
