@@ -539,7 +539,7 @@ int frpca_run(frpca_t h, int k, int p_passes, int s_oversample, uint64_t seed, f
     };
     auto basis_from_B1 = [&] {
       frpca_ctx::Scope t(h, FRPCA_T_TSMM);
-      launch_tsmm(h->X, false, LP, Ns, l, h->B1, LP, l, LP, h->Q, LP, bf ? h->Qb : nullptr, LP, false, st);
+      launch_tsmm(h->X, false, LP, Ns, l, h->B1, LP, l, LP, h->Q, LP, bf ? h->Qb : nullptr, LP, st);
     };
     auto orth_lu = [&] {
       {
@@ -591,11 +591,11 @@ int frpca_run(frpca_t h, int k, int p_passes, int s_oversample, uint64_t seed, f
     float* out_short = a6 ? V : U;
     auto tsmm_long = [&] {
       frpca_ctx::Scope t(h, FRPCA_T_TSMM);
-      launch_tsmm(h->Z, false, LP, Nl, l, h->B1, LP, k, k, out_long, k, nullptr, 0, false, st);
+      launch_tsmm(h->Z, false, LP, Nl, l, h->B1, LP, k, k, out_long, k, nullptr, 0, st);
     };
     auto tsmm_short = [&] {
       frpca_ctx::Scope t(h, FRPCA_T_TSMM);
-      launch_tsmm(h->Q, false, LP, Ns, l, h->B2, LP, k, k, out_short, k, nullptr, 0, false, st);
+      launch_tsmm(h->Q, false, LP, Ns, l, h->B2, LP, k, k, out_short, k, nullptr, 0, st);
     };
     if (a6) {  // V is the short-side output: build it, fix signs, then U
       tsmm_short();
@@ -675,12 +675,10 @@ int frpca_backward(frpca_t h, int k, const float* U, const float* S, const float
       if (dU) launch_gram(U, false, k, dU, k, m, k, part, J, k, st);
       if (dV) launch_gram(V, false, k, dV, k, n, k, part, K, k, st);
       launch_adjoint_small(J, K, S, dS, k, dU != nullptr, dV != nullptr, CU, CV, SP, st);
-      launch_tsmm(U, false, k, m, k, CU, k, k, k, L1, k, nullptr, 0, false, st);
-      if (dU) launch_tsmm(dU, false, k, m, k, SP, k, k, k, L1, k, nullptr, 0, true, st);
-      if (dV) {
-        launch_tsmm(V, false, k, n, k, CV, k, k, k, R2, k, nullptr, 0, false, st);
-        launch_tsmm(dV, false, k, n, k, SP, k, k, k, R2, k, nullptr, 0, true, st);
-      }
+      // L1 = U CU + dU SP and R2 = V CV + dV SP, SP diagonal: one pass each, the dU (dV)
+      // term added in the product's epilogue
+      launch_tsmm(U, false, k, m, k, CU, k, k, k, L1, k, nullptr, 0, st, dU, k, dU ? SP : nullptr, k);
+      if (dV) launch_tsmm(V, false, k, n, k, CV, k, k, k, R2, k, nullptr, 0, st, dV, k, SP, k);
       if (cen) {
         launch_wsum(L1, false, k, m, k, nullptr, 1.0 / (double)m, wpart, ell, st);
         if (dV) launch_wsum(U, false, k, m, k, nullptr, 1.0 / (double)m, wpart, ell + kMaxL, st);
@@ -804,7 +802,7 @@ int frpca_eigsvd(frpca_t h, int64_t rows, int l, const float* X, int ldx, float*
     launch_gram(X, false, ldx, nullptr, 0, rows, l, static_cast<double*>(part.p), G, l, st, h->opts.gram_f32 != 0);
     launch_eig(G, l, l, d, W, static_cast<double*>(etmp.p), st);
     launch_eigsvd_coeffs(d, W, l, l, tol, B, S, st);
-    launch_tsmm(X, false, ldx, rows, l, B, l, l, l, Q, ldq, nullptr, 0, false, st);
+    launch_tsmm(X, false, ldx, rows, l, B, l, l, l, Q, ldq, nullptr, 0, st);
     check_launch();
     FRPCA_HIP(hipStreamSynchronize(st));
   });
@@ -820,7 +818,7 @@ int frpca_lu(frpca_t h, int64_t rows, int l, const float* X, int ldx, float* Q, 
     DeviceTemp tmp(lu_temp_bytes(rows, l)), B(kMaxL * kMaxL * sizeof(double)), nd(256);
     hipStream_t st = h->stream;
     launch_lu_coeffs(X, ldx, rows, l, tol, static_cast<double*>(B.p), l, tmp.p, static_cast<int*>(nd.p), st);
-    launch_tsmm(X, false, ldx, rows, l, static_cast<double*>(B.p), l, l, l, Q, ldq, nullptr, 0, false, st);
+    launch_tsmm(X, false, ldx, rows, l, static_cast<double*>(B.p), l, l, l, Q, ldq, nullptr, 0, st);
     check_launch();
     int hnd = 0;
     FRPCA_HIP(hipMemcpyAsync(&hnd, nd.p, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -836,7 +834,7 @@ int frpca_tsmm(frpca_t h, int64_t rows, int kdim, int c, const float* X, int ldx
     FRPCA_CHECK(rows >= 0 && kdim >= 1 && kdim <= kMaxL && c >= 1 && c <= kMaxL && ldx >= kdim && ldo >= c && X &&
                     B && out,
                 FRPCA_EINVAL, "bad TSMM arguments");
-    launch_tsmm(X, false, ldx, rows, kdim, B, c, c, c, out, ldo, nullptr, 0, false, h->stream);
+    launch_tsmm(X, false, ldx, rows, kdim, B, c, c, c, out, ldo, nullptr, 0, h->stream);
     check_launch();
     FRPCA_HIP(hipStreamSynchronize(h->stream));
   });

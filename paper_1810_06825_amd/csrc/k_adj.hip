@@ -77,9 +77,10 @@ __global__ __launch_bounds__(256) void sddmm_kernel(const int32_t* rp, const int
 }
 
 // Paired form (k a multiple of 4, rows 16-byte aligned): lanes 0-31 take the even nonzero of
-// each pair of a row, lanes 32-63 the odd one, a lane covering four columns; eight pairs are
-// gathered before any is reduced, and each half-wave sum runs on DPP row shifts (lanes 31 and
-// 63 end with the totals), so no LDS shuffles are needed.
+// each pair of a row, lanes 32-63 the odd one, a lane covering four columns; the column
+// indices come 64 at a time in one coalesced load and reach the pairs by readlane; eight pairs
+// are gathered before any is reduced, and each half-wave sum runs on DPP row shifts (lanes 31
+// and 63 end with the totals), so no LDS shuffles are needed.
 constexpr int kSdPairs = 8;
 
 template <int CTRL, int ROW_MASK>
@@ -112,28 +113,36 @@ __global__ __launch_bounds__(256) void sddmm4_kernel(const int32_t* rp, const in
     if (act) x = *reinterpret_cast<const float4*>(P1 + (size_t)r * w + c4);
     if (P2 && act) y = *reinterpret_cast<const float4*>(P2 + (size_t)r * w + c4);
     const int e0 = rp[r], e1 = rp[r + 1];
-    for (int e = e0; e < e1; e += 2 * kSdPairs) {
-      float part[kSdPairs];
-      int cs[kSdPairs];
+    for (int ec = e0; ec < e1; ec += 64) {
+      // 64 column indices per coalesced load, handed to the pairs by readlane
+      const int cidx = ec + lane < e1 ? col[ec + lane] : 0;
+      const int nb = min(64, e1 - ec);
+      for (int b = 0; b < nb; b += 2 * kSdPairs) {
+        const int e = ec + b;
+        float part[kSdPairs];
+        int cs[kSdPairs];
 #pragma unroll
-      for (int p = 0; p < kSdPairs; ++p) {
-        const int ee = e + 2 * p + half;
-        const bool ok = ee < e1;
-        const int c = ok ? col[ee] : 0;
-        cs[p] = c;
-        const float4 q = *reinterpret_cast<const float4*>(Q1 + (size_t)c * w + gc);
-        float s = x.x * q.x + x.y * q.y + x.z * q.z + x.w * q.w;
-        if (Q2) {
-          const float4 q2 = *reinterpret_cast<const float4*>(Q2 + (size_t)c * w + gc);
-          s += y.x * q2.x + y.y * q2.y + y.z * q2.z + y.w * q2.w;
+        for (int p = 0; p < kSdPairs; ++p) {
+          const int ee = e + 2 * p + half;
+          const bool ok = ee < e1;
+          const int ce = __builtin_amdgcn_readlane(cidx, b + 2 * p);
+          const int co = __builtin_amdgcn_readlane(cidx, b + 2 * p + 1);
+          const int c = half ? co : ce;
+          cs[p] = c;
+          const float4 q = *reinterpret_cast<const float4*>(Q1 + (size_t)c * w + gc);
+          float s = x.x * q.x + x.y * q.y + x.z * q.z + x.w * q.w;
+          if (Q2) {
+            const float4 q2 = *reinterpret_cast<const float4*>(Q2 + (size_t)c * w + gc);
+            s += y.x * q2.x + y.y * q2.y + y.z * q2.z + y.w * q2.w;
+          }
+          part[p] = (ok && act) ? s : 0.f;
         }
-        part[p] = (ok && act) ? s : 0.f;
-      }
 #pragma unroll
-      for (int p = 0; p < kSdPairs; ++p) {
-        const float t = half_sum_last(part[p]);
-        const int ee = e + 2 * p + half;
-        if ((lane & 31) == 31 && ee < e1) dval[ee] = corr ? t - corr[cs[p]] : t;
+        for (int p = 0; p < kSdPairs; ++p) {
+          const float t = half_sum_last(part[p]);
+          const int ee = e + 2 * p + half;
+          if ((lane & 31) == 31 && ee < e1) dval[ee] = corr ? t - corr[cs[p]] : t;
+        }
       }
     }
   }

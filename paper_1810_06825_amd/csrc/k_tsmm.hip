@@ -32,8 +32,11 @@ struct TsmmArgs {
   int ldo;
   uint16_t* out_bf16;
   int ldo16;
-  int accumulate;
   int vec;    // rows of X allow 4-wide vector loads
+  const float* y2;   // optional second term y2 diag(d2): out += y2[r, c] d2[c, c]
+  int ldy2;
+  const double* d2;
+  int ldd2;
 };
 
 // k is visited in groups of 16: lane l (group j = l/16, row lr = l%16) loads the four
@@ -78,10 +81,13 @@ __global__ __launch_bounds__(kTsmmThreads) void tsmm_kernel(TsmmArgs a) {
   constexpr int CP = NCT * 16;
   constexpr int LDS_LD = CP + 2;  // pad rows so the 4 k-rows of an operand fetch use distinct banks
   __shared__ double Bs[KP * LDS_LD];
+  __shared__ double Ds[CP];  // diagonal of d2 (second term)
   for (int i = threadIdx.x; i < KP * CP; i += kTsmmThreads) {
     const int r = i / CP, cc = i - r * CP;
     Bs[r * LDS_LD + cc] = (r < a.kdim && cc < a.c) ? a.B[(size_t)r * a.ldb + cc] : 0.0;
   }
+  if (a.y2)
+    for (int i = threadIdx.x; i < CP; i += kTsmmThreads) Ds[i] = i < a.c ? a.d2[(size_t)i * a.ldd2 + i] : 0.0;
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int lr = lane & 15, lk = lane >> 4;
@@ -116,6 +122,21 @@ __global__ __launch_bounds__(kTsmmThreads) void tsmm_kernel(TsmmArgs a) {
       // exhaust the register file)
       __builtin_amdgcn_sched_barrier(0);
     }
+    if (a.y2) {
+      // the second term's entries, all loaded before any is used (row and column clamped
+      // into the panel; the clamped ones meet a zero in Ds or are not stored)
+#pragma unroll
+      for (int j = 0; j < NCT; ++j) {
+        const int col = 16 * j + lr;
+        const int cl = col < a.c ? col : a.c - 1;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int64_t row = r0 + lk + 4 * q;
+          const int64_t rl = row < a.rows ? row : a.rows - 1;
+          acc[j][q] += (double)a.y2[(size_t)rl * a.ldy2 + cl] * Ds[col];
+        }
+      }
+    }
 #pragma unroll
     for (int j = 0; j < NCT; ++j) {
       const int col = 16 * j + lr;
@@ -123,12 +144,9 @@ __global__ __launch_bounds__(kTsmmThreads) void tsmm_kernel(TsmmArgs a) {
       for (int q = 0; q < 4; ++q) {
         const int64_t row = r0 + lk + 4 * q;
         if (row < a.rows && col < a.c_out) {
-          float v = (col < a.c) ? (float)acc[j][q] : 0.0f;
-          if (a.out) {
-            float* o = a.out + (size_t)row * a.ldo + col;
-            if (a.accumulate && col < a.c) v = (float)((double)*o + acc[j][q]);
-            *o = v;
-          }
+          const double t = acc[j][q];
+          float v = (col < a.c) ? (float)t : 0.0f;
+          if (a.out) a.out[(size_t)row * a.ldo + col] = v;
           if (a.out_bf16) a.out_bf16[(size_t)row * a.ldo16 + col] = f32_to_bf16(v);
         }
       }
@@ -163,11 +181,13 @@ void tsmm_dispatch(int nkt, int nct, unsigned grid, const TsmmArgs& a, hipStream
 }  // namespace
 
 void launch_tsmm(const void* X, bool x_bf16, int ldx, int64_t rows, int kdim, const double* B, int ldb, int c,
-                 int c_out, float* out, int ldo, uint16_t* out_bf16, int ldo16, bool accumulate, hipStream_t st) {
+                 int c_out, float* out, int ldo, uint16_t* out_bf16, int ldo16, hipStream_t st,
+                 const float* y2, int ldy2, const double* d2, int ldd2) {
   if (rows <= 0 || c_out <= 0) return;
   const uintptr_t xa = reinterpret_cast<uintptr_t>(X);
   const int vec = x_bf16 ? ((ldx % 4) == 0 && (xa % 8) == 0) : ((ldx % 4) == 0 && (xa % 16) == 0);
-  TsmmArgs a{X, ldx, rows, kdim, B, ldb, c, c_out, out, ldo, out_bf16, ldo16, accumulate ? 1 : 0, vec};
+  TsmmArgs a{X, ldx, rows, kdim, B, ldb, c, c_out, out, ldo, out_bf16, ldo16, vec,
+             y2, ldy2, d2, ldd2};
   const int nkt = (kdim + 3) / 4;
   const int nct = (c_out + 15) / 16;
   const int64_t ntiles = (rows + 15) / 16;

@@ -112,11 +112,13 @@ void launch_spmm(const MergePlan& p, int lp, const void* in, bool in_bf16, int l
 size_t gram_partial_bytes(int l);
 void launch_gram(const void* X1, bool bf16, int ld1, const float* X2, int ld2, int64_t rows,
                  int l, double* partial, double* G, int ldg, hipStream_t st, bool f32_mfma = false);
-// out[rows x c_out] = X[rows x kdim] B[kdim x c] (+ out if accumulate); columns c..c_out-1
-// written as 0. FP64 MFMA accumulation. out_bf16 (optional) receives a BF16 copy.
+// out[rows x c_out] = X[rows x kdim] B[kdim x c] (+ y2 diag(d2) when y2 is given); columns
+// c..c_out-1 written as 0. FP64 MFMA accumulation, the y2 term added in FP64 before the one
+// rounding to FP32. out (optional) and out_bf16 (optional) receive FP32 and BF16 results.
 void launch_tsmm(const void* X, bool x_bf16, int ldx, int64_t rows, int kdim, const double* B,
                  int ldb, int c, int c_out, float* out, int ldo, uint16_t* out_bf16, int ldo16,
-                 bool accumulate, hipStream_t st);
+                 hipStream_t st, const float* y2 = nullptr, int ldy2 = 0, const double* d2 = nullptr,
+                 int ldd2 = 0);
 
 // Symmetric eigendecomposition (G: l x l FP64, ldg): Householder tridiagonalization, then
 // relatively robust representations (three launches). d ascending, W l x l row-major
