@@ -106,8 +106,8 @@ def main():
         copy_calibration()
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported by this build "
-              "(the multi-GPU sharding is a design note, not an implementation)", file=sys.stderr)
+        print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
+              "(the row-partitioned multi-GPU scheme is described, not implemented)", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
