@@ -107,10 +107,12 @@ __device__ __forceinline__ void gram_load(const float* X, int ld, int64_t row, b
 #endif
 constexpr int kGramRing = FRPCA_GRAM_RING;  // row buffers per wave on the padded-panel path (0: off)
 
-// Unconditional load of one row for panels whose leading dimension covers every tile column
-// (ld >= 16 NT, 16-byte aligned rows); rows past r1 read row r1 - 1 (such loads only fill the
-// pipeline past the last step and are never used). Columns past l come from the padding: a
-// column only enters the Gram entries of its own row and column, which the reduction drops.
+// Unconditional load of one row (16-byte aligned rows) whose 16 NT tile columns lie inside the
+// panel: either ld >= 16 NT, or ld >= 8 NT and the row is not the panel's last (the columns past
+// ld are then the next row's first ones). Rows past r1 read row r1 - 1 (such loads only fill
+// the pipeline past the last step and are never used). Columns past l come from the padding or
+// the next row: a column only enters the Gram entries of its own row and column, which the
+// reduction drops.
 template <int NT>
 __device__ __forceinline__ void gram_load_wide(const float* X, int ld, int64_t row, int64_t r1, int cc,
                                                float v[NT]) {
@@ -133,7 +135,7 @@ __device__ __forceinline__ void gram_load_wide(const float* X, int ld, int64_t r
 
 template <int NT, bool SYM, int PG, bool F32>
 __device__ __forceinline__ void gram_wave(const float* X1, int ld1, const float* X2, int ld2, int vec, int64_t r0,
-                                          int64_t r1, int half, int l, double* out, double* lds) {
+                                          int64_t r1, int64_t rows, int half, int l, double* out, double* lds) {
   constexpr int NP = npairs(NT, SYM);
   constexpr int PPW = (NP - PG + 3) / 4;  // pairs p = PG + 4q
   const int lane = threadIdx.x & 63;
@@ -183,7 +185,7 @@ __device__ __forceinline__ void gram_wave(const float* X1, int ld1, const float*
     }
   };
   int64_t r = r0 + 4 * half;
-  if (kGramRing > 0 && vec == 2 && r1 > r0 && ((r1 - r0) & 7) == 0) {
+  if (kGramRing > 0 && (vec == 2 || (vec == 3 && r1 < rows)) && r1 > r0 && ((r1 - r0) & 7) == 0) {
     // every step of the stretch is full: a ring of kGramRing row buffers, each refilled
     // kGramRing - 1 steps before its step, with a wave-uniform step count
     constexpr int D = kGramRing > 0 ? kGramRing : 1;
@@ -267,10 +269,10 @@ __global__ __launch_bounds__(kGramThreads) void gram_kernel(const float* X1, int
   // the wave index as a scalar: the row loops and the tile-group switch branch uniformly
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), half = w >> 2;
   switch (w & 3) {
-    case 0: gram_wave<NT, SYM, 0, F32>(X1, ld1, X2, ld2, vec, r0, r1, half, l, out, lds); break;
-    case 1: gram_wave<NT, SYM, 1, F32>(X1, ld1, X2, ld2, vec, r0, r1, half, l, out, lds); break;
-    case 2: gram_wave<NT, SYM, 2, F32>(X1, ld1, X2, ld2, vec, r0, r1, half, l, out, lds); break;
-    default: gram_wave<NT, SYM, 3, F32>(X1, ld1, X2, ld2, vec, r0, r1, half, l, out, lds); break;
+    case 0: gram_wave<NT, SYM, 0, F32>(X1, ld1, X2, ld2, vec, r0, r1, rows, half, l, out, lds); break;
+    case 1: gram_wave<NT, SYM, 1, F32>(X1, ld1, X2, ld2, vec, r0, r1, rows, half, l, out, lds); break;
+    case 2: gram_wave<NT, SYM, 2, F32>(X1, ld1, X2, ld2, vec, r0, r1, rows, half, l, out, lds); break;
+    default: gram_wave<NT, SYM, 3, F32>(X1, ld1, X2, ld2, vec, r0, r1, rows, half, l, out, lds); break;
   }
 }
 
@@ -343,10 +345,12 @@ void launch_gram(const void* X1, bool /*bf16*/, int ld1, const float* X2, int ld
   const bool sym = (X2 == nullptr);
   const float* x1 = static_cast<const float*>(X1);
   auto aligned = [](const float* x, int ld) { return (ld % 4) == 0 && (reinterpret_cast<uintptr_t>(x) % 16) == 0; };
-  // 2: aligned rows whose leading dimension covers every tile column; 1: aligned rows;
-  // 0: element loads
+  // 2: aligned rows whose leading dimension covers every tile column; 3: aligned rows whose
+  // tile columns end inside the next row (unconditional loads in every block but the last);
+  // 1: aligned rows; 0: element loads
   int vec = aligned(x1, ld1) && (sym || aligned(X2, ld2)) ? 1 : 0;
   if (vec && ld1 >= 16 * nt && (sym || ld2 >= 16 * nt)) vec = 2;
+  else if (vec && 2 * ld1 >= 16 * nt && (sym || 2 * ld2 >= 16 * nt)) vec = 3;
   int64_t grid = (rows + 127) / 128;
   if (grid > kGramMaxBlocks) grid = kGramMaxBlocks;
   if (grid < 1) grid = 1;
