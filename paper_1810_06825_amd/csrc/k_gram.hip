@@ -5,7 +5,8 @@
 // Each MFMA multiplies a 16x4 tile of X^T by a 4x16 tile of X: lane l supplies
 // X[r0 + l/16][16*I + l%16] as the A operand (tile row I) and the same formula with J as the
 // B operand; the 16x16 result tile is held 4 values per lane: value q of lane l is row
-// l/16 + 4q, column l%16 (layout checked on gfx950). The l x l output is covered by NT x NT tiles (NT = ceil(l/16) rounded to even);
+// l/16 + 4q, column l%16 (layout checked on gfx950). The l x l output is covered by NT x NT tiles
+// (NT = ceil(l/16), with 1 and 5 rounded up to 2 and 6);
 // for the symmetric Gram only the NT(NT+1)/2 upper tiles are computed. The four waves of a
 // block split the tiles and walk the same rows 4 at a time. On panels padded to 16 NT columns
 // each wave keeps three row steps in flight in a ring of registers (unconditional loads, so the
@@ -64,11 +65,14 @@ constexpr int pair_j(int nt, bool sym, int p) {
 constexpr int npairs(int nt, bool sym) { return sym ? nt * (nt + 1) / 2 : nt * nt; }
 
 // Column order inside the tiles: groups of four tiles cover 64 consecutive columns (entry t of
-// tile I is column 64 (I/4) + 4t + I%4) and a trailing pair covers 32 (entry t of tile I is
-// 64 G4 + 2t + (I - 4 G4)), so a lane's operands for all tiles come from one 16-byte (or
-// 8-byte) load per group. The reduction maps the tiles back.
+// tile I is column 64 (I/4) + 4t + I%4), a trailing pair covers the next 32 (entry t of tile I
+// is 64 G4 + 2t + (I - 4 G4)) and a last single tile the 16 after those (entry t is
+// 64 G4 + 32 + t). A lane's operands for all tiles come from one 16-, 8- or 4-byte load per
+// group. The reduction maps the tiles back.
 __host__ __device__ constexpr int gram_col(int nt, int I, int t) {
-  return (I < 4 * (nt / 4)) ? 64 * (I / 4) + 4 * t + (I % 4) : 64 * (nt / 4) + 2 * t + (I - 4 * (nt / 4));
+  return (I < 4 * (nt / 4))       ? 64 * (I / 4) + 4 * t + (I % 4)
+         : (I < 4 * (nt / 4) + 2) ? 64 * (nt / 4) + 2 * t + (I - 4 * (nt / 4))
+                                  : 64 * (nt / 4) + 32 + t;
 }
 
 template <int NT>
@@ -89,7 +93,11 @@ __device__ __forceinline__ void gram_load(const float* X, int ld, int64_t row, b
       for (int q = 0; q < 4; ++q) v[4 * g + q] = (ok && c0 + q < l) ? X[(size_t)row * ld + c0 + q] : 0.f;
     }
   }
-  if constexpr (NT % 4 != 0) {
+  if constexpr (NT % 4 == 3) {
+    const int c1 = 64 * G4 + 32 + cc;
+    v[4 * G4 + 2] = (ok && c1 < l) ? X[(size_t)row * ld + c1] : 0.f;
+  }
+  if constexpr (NT % 4 >= 2) {
     const int c0 = 64 * G4 + 2 * cc;
     if (ok && vec && c0 + 1 < l) {
       const float2 w = *reinterpret_cast<const float2*>(X + (size_t)row * ld + c0);
@@ -108,8 +116,8 @@ __device__ __forceinline__ void gram_load(const float* X, int ld, int64_t row, b
 constexpr int kGramRing = FRPCA_GRAM_RING;  // row buffers per wave on the padded-panel path (0: off)
 
 // Unconditional load of one row (16-byte aligned rows) whose 16 NT tile columns lie inside the
-// panel: either ld >= 16 NT, or ld >= 8 NT and the row is not the panel's last (the columns past
-// ld are then the next row's first ones). Rows past r1 read row r1 - 1 (such loads only fill
+// panel: either ld >= 16 NT, or 2 ld >= 16 NT and the row is not the panel's last (the columns
+// past ld are then the next row's first ones). Rows past r1 read row r1 - 1 (such loads only fill
 // the pipeline past the last step and are never used). Columns past l come from the padding or
 // the next row: a column only enters the Gram entries of its own row and column, which the
 // reduction drops.
@@ -126,11 +134,12 @@ __device__ __forceinline__ void gram_load_wide(const float* X, int ld, int64_t r
     v[4 * g + 2] = w.z;
     v[4 * g + 3] = w.w;
   }
-  if constexpr (NT % 4 != 0) {
+  if constexpr (NT % 4 >= 2) {
     const float2 w = *reinterpret_cast<const float2*>(p + 64 * G4 + 2 * cc);
     v[4 * G4] = w.x;
     v[4 * G4 + 1] = w.y;
   }
+  if constexpr (NT % 4 == 3) v[4 * G4 + 2] = p[64 * G4 + 32 + cc];
 }
 
 template <int NT, bool SYM, int PG, bool F32>
@@ -328,8 +337,10 @@ void gram_dispatch(int nt, unsigned grid, const float* X1, int ld1, const float*
                    int l, int64_t rpb, double* partial, hipStream_t st) {
   switch (nt) {
     case 2: gram_kernel<2, SYM, F32><<<grid, kGramThreads, 0, st>>>(X1, ld1, X2, ld2, vec, rows, l, rpb, partial); break;
+    case 3: gram_kernel<3, SYM, F32><<<grid, kGramThreads, 0, st>>>(X1, ld1, X2, ld2, vec, rows, l, rpb, partial); break;
     case 4: gram_kernel<4, SYM, F32><<<grid, kGramThreads, 0, st>>>(X1, ld1, X2, ld2, vec, rows, l, rpb, partial); break;
     case 6: gram_kernel<6, SYM, F32><<<grid, kGramThreads, 0, st>>>(X1, ld1, X2, ld2, vec, rows, l, rpb, partial); break;
+    case 7: gram_kernel<7, SYM, F32><<<grid, kGramThreads, 0, st>>>(X1, ld1, X2, ld2, vec, rows, l, rpb, partial); break;
     default: gram_kernel<8, SYM, F32><<<grid, kGramThreads, 0, st>>>(X1, ld1, X2, ld2, vec, rows, l, rpb, partial); break;
   }
 }
@@ -340,8 +351,11 @@ size_t gram_partial_bytes(int /*l*/) { return (size_t)kGramMaxBlocks * kMaxPairs
 
 void launch_gram(const void* X1, bool /*bf16*/, int ld1, const float* X2, int ld2, int64_t rows, int l,
                  double* partial, double* G, int ldg, hipStream_t st, bool f32_mfma) {
+  // tiles of 16 columns: 1 and 5 round up to a trailing pair (2, 6); 3 and 7 end with a pair
+  // and a single tile
   int nt = (l + 15) / 16;
-  nt += nt & 1;
+  if (nt % 4 == 1) ++nt;
+  const int ext = 16 * nt;
   const bool sym = (X2 == nullptr);
   const float* x1 = static_cast<const float*>(X1);
   auto aligned = [](const float* x, int ld) { return (ld % 4) == 0 && (reinterpret_cast<uintptr_t>(x) % 16) == 0; };
@@ -349,8 +363,8 @@ void launch_gram(const void* X1, bool /*bf16*/, int ld1, const float* X2, int ld
   // tile columns end inside the next row (unconditional loads in every block but the last);
   // 1: aligned rows; 0: element loads
   int vec = aligned(x1, ld1) && (sym || aligned(X2, ld2)) ? 1 : 0;
-  if (vec && ld1 >= 16 * nt && (sym || ld2 >= 16 * nt)) vec = 2;
-  else if (vec && 2 * ld1 >= 16 * nt && (sym || 2 * ld2 >= 16 * nt)) vec = 3;
+  if (vec && ld1 >= ext && (sym || ld2 >= ext)) vec = 2;
+  else if (vec && 2 * ld1 >= ext && (sym || 2 * ld2 >= ext)) vec = 3;
   int64_t grid = (rows + 127) / 128;
   if (grid > kGramMaxBlocks) grid = kGramMaxBlocks;
   if (grid < 1) grid = 1;

@@ -170,11 +170,12 @@ void tsmm_dispatch_c(int nct, unsigned grid, const TsmmArgs& a, hipStream_t st) 
 
 template <bool BF16>
 void tsmm_dispatch(int nkt, int nct, unsigned grid, const TsmmArgs& a, hipStream_t st) {
-  // k extents are rounded up to multiples of 32 (8 k-steps of 4); vector loads need 16-byte
-  // (FP32) or 8-byte (BF16) aligned rows, which the dispatcher checks
+  // k extents are rounded up to 32, 64, 96, 112 or 128 (k-steps of 4 in groups of 16);
+  // vector loads need 16-byte (FP32) or 8-byte (BF16) aligned rows, which the dispatcher checks
   if (nkt <= 8) tsmm_dispatch_c<8, BF16>(nct, grid, a, st);
   else if (nkt <= 16) tsmm_dispatch_c<16, BF16>(nct, grid, a, st);
   else if (nkt <= 24) tsmm_dispatch_c<24, BF16>(nct, grid, a, st);
+  else if (nkt <= 28) tsmm_dispatch_c<28, BF16>(nct, grid, a, st);
   else tsmm_dispatch_c<32, BF16>(nct, grid, a, st);
 }
 

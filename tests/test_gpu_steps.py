@@ -166,7 +166,7 @@ def test_spmm_bf16_panels(trans):
     assert np.all(np.abs(got - ref) <= 2.0 ** -8 * np.abs(ref) + 1e-5 * np.abs(ref).max())
 
 
-@pytest.mark.parametrize("l", [1, 15, 60, 120, 128])
+@pytest.mark.parametrize("l", [1, 15, 40, 60, 100, 120, 128])
 def test_gram_fp64_accumulation(l):
     rows = 50_003
     X = np.random.default_rng(l).standard_normal((rows, l)).astype(np.float32)
@@ -206,7 +206,7 @@ def test_gram_padded_panel_padding_not_used(f32):
     assert np.all(np.abs(Gg - ref) <= bound)
 
 
-@pytest.mark.parametrize("l", [1, 15, 60, 128])
+@pytest.mark.parametrize("l", [1, 15, 40, 60, 100, 128])
 def test_gram_fp32_mfma_variant(l):
     """FP32 matrix-core Gram (opts.gram_f32): every FP32 partial sums 16 rows, so each entry is
     within gamma_16 (here 2 * 16 u32, one rounding per product and per addition) of
