@@ -190,8 +190,9 @@ int frpca_gram(frpca_t h, int64_t rows, int l, const float* X, int ldx, double* 
 int frpca_eig(frpca_t h, int l, const double* G, double* W, double* d);
 
 /* eigSVD basis (Alg. 2): Q = X V diag(1/S) with S ascending; S_j <= tol * max(S) gives a
- * zero column (tol <= 0 selects 1e-12). The Gram follows opts.gram_f32 as frpca_gram. X, Q: device float panels (rows x l), S: device
- * double[l] (ascending, zeroed where dropped). */
+ * zero column (tol <= 0 selects 1e-12). The Gram follows opts.gram_f32 as frpca_gram.
+ * X, Q: device float panels (rows x l), S: device double[l] (ascending, zeroed where
+ * dropped). */
 int frpca_eigsvd(frpca_t h, int64_t rows, int l, const float* X, int ldx, float* Q, int ldq,
                  double* S, double tol);
 
