@@ -7,6 +7,10 @@ bench.py (panels with leading dimension 128, k = 100, s = 20):
   10M terms, among them) against FP64 sums of the same FP32 inputs; sampled rows of
   A V = U diag(S) in FP64; and the whole method on the first 1/16 of the rows. Properties that
   hold at any size: orthonormal U and V, descending S, the sign convention, repeatability.
+* zipf_normal, 500,000 x 100,000 (15,000,000 nnz, the differentiated workload), k = 50,
+  s = 10, q = 4: the forward against the FP64 oracle on the whole matrix, and the gradient of
+  sum(sigma) + ||U W||^2 (whose second term is invariant) against its closed form
+  sum_i u_i[r] v_i[c] at every nonzero.
 * planted_blocks, 200,000 x 50,000 (50,000,000 nnz, exact sigma_i = 10^(-3 i / 200)),
   q = 3 and 5 against the FP64 oracle on the whole matrix (about a minute of CPU each), the
   leading values against the closed form, q = 1 rejected, q = 2 and 7 by their properties.
@@ -17,12 +21,12 @@ import scipy.sparse as sp
 
 import oracle
 from gpu_util import ANG_TOL, SIG_TOL, compare_triplets, np64, say
-from synth import Csr, aminer_tfidf, planted_blocks
+from synth import Csr, aminer_tfidf, planted_blocks, zipf_normal
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-from paper_1810_06825_amd import FrPCA, FrpcaError, binding  # noqa: E402
+from paper_1810_06825_amd import FrPCA, FrpcaError, binding, frpca_autograd  # noqa: E402
 
 DEV = "cuda:0"
 K, S_OVER, SEED = 100, 20, 20181015
@@ -144,6 +148,34 @@ def test_aminer_row_slice_matches_oracle(aminer):
     say("  ->", r)
     assert r["ok"], r
     assert r["prefix"] >= 10
+
+
+def test_differentiated_workload_full_size():
+    A = zipf_normal()
+    k, q, s = 50, 4, 10
+    say("full-size zipf_normal", A.m, A.n, A.nnz, f"k={k} q={q} s={s}")
+    mat = FrPCA.from_csr(A, device=DEV)
+    vals = torch.from_numpy(A.val).to(DEV).requires_grad_(True)
+    U, S, V = frpca_autograd(vals, mat, k, q, s, SEED)
+    W = torch.from_numpy(np.random.default_rng(7).standard_normal((k, 8)).astype(np.float32)).to(DEV)
+    loss = S.sum() + ((U @ W) ** 2).sum()
+    loss.backward()
+    Ug, Sg, Vg = np64(U), np64(S), np64(V)
+    g = np64(vals.grad)
+    mat.close()
+    say("  oracle (FP64, CPU)")
+    Uo, So, Vo, _ = oracle.frpca(A, k + 1, q, s - 1, SEED)
+    r = compare_triplets(Uo[:, :k], So[:k], Vo[:, :k], Ug, Sg, Vg, So, SIG_TOL, ANG_TOL)
+    say("  forward ->", r)
+    assert r["ok"], r
+    rows = np.repeat(np.arange(A.m), np.diff(A.row_ptr))
+    ref = np.empty(A.nnz)
+    for e0 in range(0, A.nnz, 1 << 21):
+        e1 = min(A.nnz, e0 + (1 << 21))
+        ref[e0:e1] = np.einsum("ij,ij->i", Ug[rows[e0:e1]], Vg[A.col[e0:e1]])
+    err = float(np.abs(g - ref).max() / np.abs(ref).max())
+    say("  gradient vs sum_i u_i[r] v_i[c]: rel err", err)
+    assert err < 1e-4
 
 
 _ORACLE = {}
