@@ -74,7 +74,29 @@ __device__ __forceinline__ void load4(const TsmmArgs& a, int64_t row, int k0, fl
   }
 }
 
-template <int NKT, int NCT, bool BF16>
+// Branch-free form for vector-aligned panels: the row is clamped into the panel and a group past
+// the row's end reads the row's first columns (k0 and ldx are multiples of 4, so the load stays
+// in the row); the caller zeroes entries past kdim. With no load under a lane-dependent branch,
+// the compiler keeps each refill where it is written and waits only for the loads it uses.
+template <bool BF16>
+__device__ __forceinline__ void load4_nb(const TsmmArgs& a, int64_t row, int k0, float v[4]) {
+  const size_t o = (size_t)(row < a.rows ? row : a.rows - 1) * a.ldx + (k0 < a.ldx ? k0 : 0);
+  if constexpr (BF16) {
+    const uint2 w = *reinterpret_cast<const uint2*>(static_cast<const uint16_t*>(a.X) + o);
+    v[0] = bf16_to_f32((uint16_t)(w.x & 0xFFFF));
+    v[1] = bf16_to_f32((uint16_t)(w.x >> 16));
+    v[2] = bf16_to_f32((uint16_t)(w.y & 0xFFFF));
+    v[3] = bf16_to_f32((uint16_t)(w.y >> 16));
+  } else {
+    const float4 w = *reinterpret_cast<const float4*>(static_cast<const float*>(a.X) + o);
+    v[0] = w.x;
+    v[1] = w.y;
+    v[2] = w.z;
+    v[3] = w.w;
+  }
+}
+
+template <int NKT, int NCT, bool BF16, bool VEC>
 __global__ __launch_bounds__(kTsmmThreads) void tsmm_kernel(TsmmArgs a) {
   constexpr int KP = NKT * 4;
   constexpr int NU = KP / 16;     // groups of 16 k
@@ -95,9 +117,12 @@ __global__ __launch_bounds__(kTsmmThreads) void tsmm_kernel(TsmmArgs a) {
   const int64_t wstride = (int64_t)gridDim.x * kTsmmWaves;
   int64_t tile = (int64_t)blockIdx.x * kTsmmWaves + (threadIdx.x >> 6);
   float xs[NU][4];
-  if (tile < ntiles) {
+  if (VEC || tile < ntiles) {
 #pragma unroll
-    for (int u = 0; u < NU; ++u) load4<BF16>(a, tile * 16 + lr, 16 * u + 4 * lk, xs[u]);
+    for (int u = 0; u < NU; ++u) {
+      if constexpr (VEC) load4_nb<BF16>(a, tile * 16 + lr, 16 * u + 4 * lk, xs[u]);
+      else load4<BF16>(a, tile * 16 + lr, 16 * u + 4 * lk, xs[u]);
+    }
   }
   for (; tile < ntiles; tile += wstride) {
     const int64_t r0 = tile * 16;
@@ -109,9 +134,14 @@ __global__ __launch_bounds__(kTsmmThreads) void tsmm_kernel(TsmmArgs a) {
     for (int u = 0; u < NU; ++u) {
       double av[4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) av[v] = (double)xs[u][v];
-      // this group's registers now refill with the next tile's slab
-      if (nxt < ntiles) load4<BF16>(a, nxt * 16 + lr, 16 * u + 4 * lk, xs[u]);
+      for (int v = 0; v < 4; ++v) {
+        if constexpr (VEC) av[v] = (16 * u + 4 * lk + v < a.kdim) ? (double)xs[u][v] : 0.0;
+        else av[v] = (double)xs[u][v];
+      }
+      // this group's registers now refill with the next tile's slab (past the last tile the
+      // branch-free form reads the panel's last row, unused)
+      if constexpr (VEC) load4_nb<BF16>(a, nxt * 16 + lr, 16 * u + 4 * lk, xs[u]);
+      else if (nxt < ntiles) load4<BF16>(a, nxt * 16 + lr, 16 * u + 4 * lk, xs[u]);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const double* brow = Bs + (16 * u + 4 * lk + v) * LDS_LD + lr;
@@ -125,6 +155,7 @@ __global__ __launch_bounds__(kTsmmThreads) void tsmm_kernel(TsmmArgs a) {
     if (a.y2) {
       // the second term's entries, all loaded before any is used (row and column clamped
       // into the panel; the clamped ones meet a zero in Ds or are not stored)
+      float yv[NCT][4];
 #pragma unroll
       for (int j = 0; j < NCT; ++j) {
         const int col = 16 * j + lr;
@@ -133,8 +164,14 @@ __global__ __launch_bounds__(kTsmmThreads) void tsmm_kernel(TsmmArgs a) {
         for (int q = 0; q < 4; ++q) {
           const int64_t row = r0 + lk + 4 * q;
           const int64_t rl = row < a.rows ? row : a.rows - 1;
-          acc[j][q] += (double)a.y2[(size_t)rl * a.ldy2 + cl] * Ds[col];
+          yv[j][q] = a.y2[(size_t)rl * a.ldy2 + cl];
         }
+      }
+#pragma unroll
+      for (int j = 0; j < NCT; ++j) {
+        const double dj = Ds[16 * j + lr];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[j][q] += (double)yv[j][q] * dj;
       }
     }
 #pragma unroll
@@ -154,29 +191,29 @@ __global__ __launch_bounds__(kTsmmThreads) void tsmm_kernel(TsmmArgs a) {
   }
 }
 
-template <int NKT, bool BF16>
+template <int NKT, bool BF16, bool VEC>
 void tsmm_dispatch_c(int nct, unsigned grid, const TsmmArgs& a, hipStream_t st) {
   switch (nct) {
-    case 1: tsmm_kernel<NKT, 1, BF16><<<grid, kTsmmThreads, 0, st>>>(a); break;
-    case 2: tsmm_kernel<NKT, 2, BF16><<<grid, kTsmmThreads, 0, st>>>(a); break;
-    case 3: tsmm_kernel<NKT, 3, BF16><<<grid, kTsmmThreads, 0, st>>>(a); break;
-    case 4: tsmm_kernel<NKT, 4, BF16><<<grid, kTsmmThreads, 0, st>>>(a); break;
-    case 5: tsmm_kernel<NKT, 5, BF16><<<grid, kTsmmThreads, 0, st>>>(a); break;
-    case 6: tsmm_kernel<NKT, 6, BF16><<<grid, kTsmmThreads, 0, st>>>(a); break;
-    case 7: tsmm_kernel<NKT, 7, BF16><<<grid, kTsmmThreads, 0, st>>>(a); break;
-    default: tsmm_kernel<NKT, 8, BF16><<<grid, kTsmmThreads, 0, st>>>(a); break;
+    case 1: tsmm_kernel<NKT, 1, BF16, VEC><<<grid, kTsmmThreads, 0, st>>>(a); break;
+    case 2: tsmm_kernel<NKT, 2, BF16, VEC><<<grid, kTsmmThreads, 0, st>>>(a); break;
+    case 3: tsmm_kernel<NKT, 3, BF16, VEC><<<grid, kTsmmThreads, 0, st>>>(a); break;
+    case 4: tsmm_kernel<NKT, 4, BF16, VEC><<<grid, kTsmmThreads, 0, st>>>(a); break;
+    case 5: tsmm_kernel<NKT, 5, BF16, VEC><<<grid, kTsmmThreads, 0, st>>>(a); break;
+    case 6: tsmm_kernel<NKT, 6, BF16, VEC><<<grid, kTsmmThreads, 0, st>>>(a); break;
+    case 7: tsmm_kernel<NKT, 7, BF16, VEC><<<grid, kTsmmThreads, 0, st>>>(a); break;
+    default: tsmm_kernel<NKT, 8, BF16, VEC><<<grid, kTsmmThreads, 0, st>>>(a); break;
   }
 }
 
-template <bool BF16>
+template <bool BF16, bool VEC>
 void tsmm_dispatch(int nkt, int nct, unsigned grid, const TsmmArgs& a, hipStream_t st) {
   // k extents are rounded up to 32, 64, 96, 112 or 128 (k-steps of 4 in groups of 16);
   // vector loads need 16-byte (FP32) or 8-byte (BF16) aligned rows, which the dispatcher checks
-  if (nkt <= 8) tsmm_dispatch_c<8, BF16>(nct, grid, a, st);
-  else if (nkt <= 16) tsmm_dispatch_c<16, BF16>(nct, grid, a, st);
-  else if (nkt <= 24) tsmm_dispatch_c<24, BF16>(nct, grid, a, st);
-  else if (nkt <= 28) tsmm_dispatch_c<28, BF16>(nct, grid, a, st);
-  else tsmm_dispatch_c<32, BF16>(nct, grid, a, st);
+  if (nkt <= 8) tsmm_dispatch_c<8, BF16, VEC>(nct, grid, a, st);
+  else if (nkt <= 16) tsmm_dispatch_c<16, BF16, VEC>(nct, grid, a, st);
+  else if (nkt <= 24) tsmm_dispatch_c<24, BF16, VEC>(nct, grid, a, st);
+  else if (nkt <= 28) tsmm_dispatch_c<28, BF16, VEC>(nct, grid, a, st);
+  else tsmm_dispatch_c<32, BF16, VEC>(nct, grid, a, st);
 }
 
 }  // namespace
@@ -200,8 +237,13 @@ void launch_tsmm(const void* X, bool x_bf16, int ldx, int64_t rows, int kdim, co
     cus = 256;
   int64_t grid = (ntiles + kTsmmWaves - 1) / kTsmmWaves;
   if (grid > cus) grid = cus;
-  if (x_bf16) tsmm_dispatch<true>(nkt, nct, (unsigned)grid, a, st);
-  else tsmm_dispatch<false>(nkt, nct, (unsigned)grid, a, st);
+  if (x_bf16) {
+    if (vec) tsmm_dispatch<true, true>(nkt, nct, (unsigned)grid, a, st);
+    else tsmm_dispatch<true, false>(nkt, nct, (unsigned)grid, a, st);
+  } else {
+    if (vec) tsmm_dispatch<false, true>(nkt, nct, (unsigned)grid, a, st);
+    else tsmm_dispatch<false, false>(nkt, nct, (unsigned)grid, a, st);
+  }
 }
 
 }  // namespace frpca
