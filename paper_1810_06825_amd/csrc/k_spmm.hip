@@ -69,7 +69,7 @@ __device__ __forceinline__ T stream_load(const T* p) {
 }
 
 template <bool IN_BF16>
-__device__ __forceinline__ void spmm_partition(const SpmmArgs& a, int64_t w, int lane) {
+__device__ __forceinline__ void spmm_partition(const SpmmArgs& a, int64_t w, int lane, int* lw) {
   const int col = 2 * lane;
   const bool act = col < a.lp;
   int seg = a.part_seg[w];
@@ -78,7 +78,16 @@ __device__ __forceinline__ void spmm_partition(const SpmmArgs& a, int64_t w, int
   const int e_stop = a.part_e[w + 1];
   // the first segment continues a segment begun by an earlier wave
   bool pending_head = (seg < a.nseg) && (a.ptr[seg] < e);
-  int next_end = (seg < seg_stop) ? a.ptr[seg + 1] : INT_MAX;
+  // segment ends (and output rows) come 64 at a time in one coalesced load, parked in the
+  // wave's LDS window and read from there: a global load at every segment end would wait for
+  // all gathers in flight (the window's own refill waits once per 64 segments)
+  int pbase = seg;
+  auto refill = [&]() {
+    lw[lane] = (pbase + 1 + lane <= a.nseg) ? a.ptr[pbase + 1 + lane] : INT_MAX;
+    if (a.out_row) lw[64 + lane] = (pbase + lane < a.nseg) ? a.out_row[pbase + lane] : 0;
+  };
+  refill();
+  int next_end = (seg < seg_stop) ? __builtin_amdgcn_readfirstlane(lw[0]) : INT_MAX;
   float2 acc = make_float2(0.f, 0.f);
 
   auto emit = [&]() {
@@ -86,7 +95,7 @@ __device__ __forceinline__ void spmm_partition(const SpmmArgs& a, int64_t w, int
       if (pending_head) {
         store2_f32(a.head, (size_t)w * 128 + col, acc);
       } else {
-        const int64_t orow = a.out_row ? a.out_row[seg] : seg;
+        const int64_t orow = a.out_row ? lw[64 + seg - pbase] : seg;
         float2 t = acc;
         if (a.csub_v) {
           const float sc = a.csub_s ? a.csub_s[orow] : 1.f;
@@ -101,7 +110,15 @@ __device__ __forceinline__ void spmm_partition(const SpmmArgs& a, int64_t w, int
     pending_head = false;
     acc = make_float2(0.f, 0.f);
     ++seg;
-    next_end = (seg < seg_stop) ? a.ptr[seg + 1] : INT_MAX;
+    if (seg < seg_stop) {
+      if (seg - pbase >= 64) {
+        pbase += 64;
+        refill();
+      }
+      next_end = __builtin_amdgcn_readfirstlane(lw[seg - pbase]);
+    } else {
+      next_end = INT_MAX;
+    }
   };
 
   // The (index, value) stream is read 64 entries at a time with one coalesced (streaming)
@@ -181,18 +198,20 @@ __device__ __forceinline__ void spmm_partition(const SpmmArgs& a, int64_t w, int
 
 template <bool IN_BF16>
 __global__ __launch_bounds__(256) void spmm_merge_kernel(SpmmArgs a) {
+  __shared__ int win[4][128];  // per wave: 64 segment ends, then 64 output rows
   const int lane = threadIdx.x & 63;
   // wave index made explicitly uniform so the partition bounds are scalar values
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  int* lw = win[wv];
   if (!a.sweep) {
     const int64_t w = (int64_t)blockIdx.x * 4 + wv;
-    if (w < a.nwaves) spmm_partition<IN_BF16>(a, w, lane);
+    if (w < a.nwaves) spmm_partition<IN_BF16>(a, w, lane, lw);
     return;
   }
   for (int64_t round = 0;; ++round) {
     const int64_t w = sweep_block(round) * 4 + wv;
     if (w >= a.nwaves) break;
-    spmm_partition<IN_BF16>(a, w, lane);
+    spmm_partition<IN_BF16>(a, w, lane, lw);
   }
 }
 
@@ -228,7 +247,7 @@ __device__ __forceinline__ void fma4(float4& acc, float v, const float4& x) {
 }
 
 template <bool IN_BF16>
-__device__ __forceinline__ void spmm_partition4(const SpmmArgs& a, int64_t w, int lane) {
+__device__ __forceinline__ void spmm_partition4(const SpmmArgs& a, int64_t w, int lane, int* lw) {
   const int half = lane >> 5;
   const int col = 4 * (lane & 31);
   const bool act = col < a.lp;
@@ -238,7 +257,16 @@ __device__ __forceinline__ void spmm_partition4(const SpmmArgs& a, int64_t w, in
   int e = a.part_e[w];
   const int e_stop = a.part_e[w + 1];
   bool pending_head = (seg < a.nseg) && (a.ptr[seg] < e);
-  int next_end = (seg < seg_stop) ? a.ptr[seg + 1] : INT_MAX;
+  // segment ends (and output rows) come 64 at a time in one coalesced load, parked in the
+  // wave's LDS window and read from there: a global load at every segment end would wait for
+  // all gathers in flight (the window's own refill waits once per 64 segments)
+  int pbase = seg;
+  auto refill = [&]() {
+    lw[lane] = (pbase + 1 + lane <= a.nseg) ? a.ptr[pbase + 1 + lane] : INT_MAX;
+    if (a.out_row) lw[64 + lane] = (pbase + lane < a.nseg) ? a.out_row[pbase + lane] : 0;
+  };
+  refill();
+  int next_end = (seg < seg_stop) ? __builtin_amdgcn_readfirstlane(lw[0]) : INT_MAX;
   float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
 
   auto emit = [&]() {
@@ -251,7 +279,7 @@ __device__ __forceinline__ void spmm_partition4(const SpmmArgs& a, int64_t w, in
       if (pending_head) {
         *reinterpret_cast<float4*>(a.head + (size_t)w * 128 + col) = t;
       } else {
-        const int64_t orow = a.out_row ? a.out_row[seg] : seg;
+        const int64_t orow = a.out_row ? lw[64 + seg - pbase] : seg;
         if (a.csub_v) {
           const float sc = a.csub_s ? a.csub_s[orow] : 1.f;
           const float4 cv = *reinterpret_cast<const float4*>(a.csub_v + col);
@@ -273,7 +301,15 @@ __device__ __forceinline__ void spmm_partition4(const SpmmArgs& a, int64_t w, in
     pending_head = false;
     acc = make_float4(0.f, 0.f, 0.f, 0.f);
     ++seg;
-    next_end = (seg < seg_stop) ? a.ptr[seg + 1] : INT_MAX;
+    if (seg < seg_stop) {
+      if (seg - pbase >= 64) {
+        pbase += 64;
+        refill();
+      }
+      next_end = __builtin_amdgcn_readfirstlane(lw[seg - pbase]);
+    } else {
+      next_end = INT_MAX;
+    }
   };
 
   int wbase = e;
@@ -348,17 +384,19 @@ __device__ __forceinline__ void spmm_partition4(const SpmmArgs& a, int64_t w, in
 
 template <bool IN_BF16>
 __global__ __launch_bounds__(256) void spmm_merge4_kernel(SpmmArgs a) {
+  __shared__ int win[4][128];  // per wave: 64 segment ends, then 64 output rows
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  int* lw = win[wv];
   if (!a.sweep) {
     const int64_t w = (int64_t)blockIdx.x * 4 + wv;
-    if (w < a.nwaves) spmm_partition4<IN_BF16>(a, w, lane);
+    if (w < a.nwaves) spmm_partition4<IN_BF16>(a, w, lane, lw);
     return;
   }
   for (int64_t round = 0;; ++round) {
     const int64_t w = sweep_block(round) * 4 + wv;
     if (w >= a.nwaves) break;
-    spmm_partition4<IN_BF16>(a, w, lane);
+    spmm_partition4<IN_BF16>(a, w, lane, lw);
   }
 }
 
