@@ -99,6 +99,10 @@ __device__ __forceinline__ float half_sum_last(float v) {
   return v;
 }
 
+// TWO: the second product term is present; CORR: the per-column centring term is present. Both
+// are compile-time so the kSdPairs gathers of a batch issue back to back before any arithmetic
+// (a run-time test between them makes the compiler wait for each gather in turn).
+template <bool TWO, bool CORR>
 __global__ __launch_bounds__(256) void sddmm4_kernel(const int32_t* rp, const int32_t* col, int64_t m, int w,
                                                      const float* P1, const float* Q1, const float* P2,
                                                      const float* Q2, const float* corr, float* dval) {
@@ -109,39 +113,37 @@ __global__ __launch_bounds__(256) void sddmm4_kernel(const int32_t* rp, const in
   const int64_t wave0 = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t wstride = (int64_t)gridDim.x * 4;
   for (int64_t r = wave0; r < m; r += wstride) {
-    float4 x = make_float4(0.f, 0.f, 0.f, 0.f), y = x;
-    if (act) x = *reinterpret_cast<const float4*>(P1 + (size_t)r * w + c4);
-    if (P2 && act) y = *reinterpret_cast<const float4*>(P2 + (size_t)r * w + c4);
+    // inactive lanes read column 0 of the row (in bounds); their products are dropped below
+    const float4 x = *reinterpret_cast<const float4*>(P1 + (size_t)r * w + gc);
+    float4 y = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (TWO) y = *reinterpret_cast<const float4*>(P2 + (size_t)r * w + gc);
     const int e0 = rp[r], e1 = rp[r + 1];
     for (int ec = e0; ec < e1; ec += 64) {
-      // 64 column indices per coalesced load, handed to the pairs by readlane
+      // 64 column indices per coalesced load, handed to the pairs by readlane; past the row end
+      // the index is 0, a valid column whose result is discarded
       const int cidx = ec + lane < e1 ? col[ec + lane] : 0;
-      const int nb = min(64, e1 - ec);
+      const int nb = __builtin_amdgcn_readfirstlane(min(64, e1 - ec));
       for (int b = 0; b < nb; b += 2 * kSdPairs) {
         const int e = ec + b;
-        float part[kSdPairs];
         int cs[kSdPairs];
+        float4 q[kSdPairs], q2[kSdPairs];
+        float cv[kSdPairs];
 #pragma unroll
         for (int p = 0; p < kSdPairs; ++p) {
-          const int ee = e + 2 * p + half;
-          const bool ok = ee < e1;
-          const int ce = __builtin_amdgcn_readlane(cidx, b + 2 * p);
-          const int co = __builtin_amdgcn_readlane(cidx, b + 2 * p + 1);
-          const int c = half ? co : ce;
-          cs[p] = c;
-          const float4 q = *reinterpret_cast<const float4*>(Q1 + (size_t)c * w + gc);
-          float s = x.x * q.x + x.y * q.y + x.z * q.z + x.w * q.w;
-          if (Q2) {
-            const float4 q2 = *reinterpret_cast<const float4*>(Q2 + (size_t)c * w + gc);
-            s += y.x * q2.x + y.y * q2.y + y.z * q2.z + y.w * q2.w;
-          }
-          part[p] = (ok && act) ? s : 0.f;
+          const int ce = __builtin_amdgcn_readlane(cidx, (b + 2 * p) & 63);
+          const int co = __builtin_amdgcn_readlane(cidx, (b + 2 * p + 1) & 63);
+          cs[p] = half ? co : ce;
+          q[p] = *reinterpret_cast<const float4*>(Q1 + (size_t)cs[p] * w + gc);
+          if (TWO) q2[p] = *reinterpret_cast<const float4*>(Q2 + (size_t)cs[p] * w + gc);
+          if (CORR) cv[p] = corr[cs[p]];
         }
 #pragma unroll
         for (int p = 0; p < kSdPairs; ++p) {
-          const float t = half_sum_last(part[p]);
+          float s = x.x * q[p].x + x.y * q[p].y + x.z * q[p].z + x.w * q[p].w;
+          if (TWO) s += y.x * q2[p].x + y.y * q2[p].y + y.z * q2[p].z + y.w * q2[p].w;
+          const float t = half_sum_last(act ? s : 0.f);
           const int ee = e + 2 * p + half;
-          if ((lane & 31) == 31 && ee < e1) dval[ee] = corr ? t - corr[cs[p]] : t;
+          if ((lane & 31) == 31 && ee < e1) dval[ee] = CORR ? t - cv[p] : t;
         }
       }
     }
@@ -162,7 +164,11 @@ void launch_sddmm(const int32_t* rp, const int32_t* col, int64_t m, int w, const
   if (grid > 65536) grid = 65536;
   auto al = [](const float* p) { return p == nullptr || (reinterpret_cast<uintptr_t>(p) % 16) == 0; };
   if (w % 4 == 0 && w <= 128 && al(P1) && al(Q1) && al(P2) && al(Q2)) {
-    sddmm4_kernel<<<(unsigned)grid, 256, 0, st>>>(rp, col, m, w, P1, Q1, P2, Q2, corr, dval);
+    const bool two = P2 != nullptr && Q2 != nullptr;
+    if (two && corr) sddmm4_kernel<true, true><<<(unsigned)grid, 256, 0, st>>>(rp, col, m, w, P1, Q1, P2, Q2, corr, dval);
+    else if (two) sddmm4_kernel<true, false><<<(unsigned)grid, 256, 0, st>>>(rp, col, m, w, P1, Q1, P2, Q2, corr, dval);
+    else if (corr) sddmm4_kernel<false, true><<<(unsigned)grid, 256, 0, st>>>(rp, col, m, w, P1, Q1, P2, Q2, corr, dval);
+    else sddmm4_kernel<false, false><<<(unsigned)grid, 256, 0, st>>>(rp, col, m, w, P1, Q1, P2, Q2, corr, dval);
     return;
   }
   sddmm_kernel<<<(unsigned)grid, 256, 0, st>>>(rp, col, m, w, P1, Q1, P2, Q2, corr, dval);
