@@ -112,16 +112,42 @@ __global__ __launch_bounds__(256) void sddmm4_kernel(const int32_t* rp, const in
   const int gc = act ? c4 : 0;
   const int64_t wave0 = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t wstride = (int64_t)gridDim.x * 4;
-  for (int64_t r = wave0; r < m; r += wstride) {
-    // inactive lanes read column 0 of the row (in bounds); their products are dropped below
-    const float4 x = *reinterpret_cast<const float4*>(P1 + (size_t)r * w + gc);
-    float4 y = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (TWO) y = *reinterpret_cast<const float4*>(P2 + (size_t)r * w + gc);
-    const int e0 = rp[r], e1 = rp[r + 1];
-    for (int ec = e0; ec < e1; ec += 64) {
-      // 64 column indices per coalesced load, handed to the pairs by readlane; past the row end
-      // the index is 0, a valid column whose result is discarded
-      const int cidx = ec + lane < e1 ? col[ec + lane] : 0;
+  int64_t r = wave0;
+  if (r >= m) return;
+  // The metadata of a row (its panel entries x, y and its first 64 column indices) is loaded
+  // one row ahead and its extent two rows ahead, so a row's first gathers do not wait for the
+  // row pointer and then the column indices in turn. Inactive lanes read column 0 of a panel
+  // row (in bounds); their products are dropped below.
+  auto load_x = [&](int64_t row, float4& xo, float4& yo) {
+    xo = *reinterpret_cast<const float4*>(P1 + (size_t)row * w + gc);
+    yo = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (TWO) yo = *reinterpret_cast<const float4*>(P2 + (size_t)row * w + gc);
+  };
+  int e0 = rp[r], e1 = rp[r + 1];
+  float4 x, y;
+  load_x(r, x, y);
+  int cidx = e0 + lane < e1 ? col[e0 + lane] : 0;
+  int64_t rn = r + wstride;
+  int e0n = 0, e1n = 0;
+  if (rn < m) {
+    e0n = rp[rn];
+    e1n = rp[rn + 1];
+  }
+  for (;;) {
+    float4 xn = x, yn = y;
+    int cidxn = 0, e0nn = 0, e1nn = 0;
+    const int64_t rnn = rn + wstride;
+    if (rn < m) {
+      load_x(rn, xn, yn);
+      cidxn = e0n + lane < e1n ? col[e0n + lane] : 0;
+      if (rnn < m) {
+        e0nn = rp[rnn];
+        e1nn = rp[rnn + 1];
+      }
+    }
+    // one chunk of up to 64 nonzeros whose column indices the lanes hold in ci; past the row end
+    // the index is 0, a valid column whose result is discarded
+    auto chunk = [&](int ec, int ci) {
       const int nb = __builtin_amdgcn_readfirstlane(min(64, e1 - ec));
       for (int b = 0; b < nb; b += 2 * kSdPairs) {
         const int e = ec + b;
@@ -130,8 +156,8 @@ __global__ __launch_bounds__(256) void sddmm4_kernel(const int32_t* rp, const in
         float cv[kSdPairs];
 #pragma unroll
         for (int p = 0; p < kSdPairs; ++p) {
-          const int ce = __builtin_amdgcn_readlane(cidx, (b + 2 * p) & 63);
-          const int co = __builtin_amdgcn_readlane(cidx, (b + 2 * p + 1) & 63);
+          const int ce = __builtin_amdgcn_readlane(ci, (b + 2 * p) & 63);
+          const int co = __builtin_amdgcn_readlane(ci, (b + 2 * p + 1) & 63);
           cs[p] = half ? co : ce;
           q[p] = *reinterpret_cast<const float4*>(Q1 + (size_t)cs[p] * w + gc);
           if (TWO) q2[p] = *reinterpret_cast<const float4*>(Q2 + (size_t)cs[p] * w + gc);
@@ -146,7 +172,21 @@ __global__ __launch_bounds__(256) void sddmm4_kernel(const int32_t* rp, const in
           if ((lane & 31) == 31 && ee < e1) dval[ee] = CORR ? t - cv[p] : t;
         }
       }
-    }
+    };
+    // The first chunk is a code path of its own: its indices arrived with the previous row, so
+    // its gathers issue without waiting for the loads just issued for the next row.
+    if (e0 < e1) chunk(e0, cidx);
+    for (int ec = e0 + 64; ec < e1; ec += 64) chunk(ec, ec + lane < e1 ? col[ec + lane] : 0);
+    if (rn >= m) break;
+    r = rn;
+    rn = rnn;
+    x = xn;
+    y = yn;
+    cidx = cidxn;
+    e0 = e0n;
+    e1 = e1n;
+    e0n = e0nn;
+    e1n = e1nn;
   }
 }
 
