@@ -172,6 +172,9 @@ __global__ __launch_bounds__(kNode) void lu_select_kernel(SelectArgs a) {
   // update runs over whole 8-column chunks; columns left of the pivot are finished and
   // never read again, so updating them is harmless.
   constexpr int NC = LP / 8;
+  // chunks per update group: four at the widest panel, whose registers already limit a CU to
+  // one block; narrower panels keep one chunk per group, so two blocks still fit on a CU
+  constexpr int NG = LP >= 128 ? 4 : 1;
   int cnt = 0;
   for (int jb = 0; jb < NC; ++jb) {
 #pragma unroll
@@ -206,19 +209,25 @@ __global__ __launch_bounds__(kNode) void lu_select_kernel(SelectArgs a) {
             // the multiplier only steers which rows survive the tournament (the pivot rows are
             // refactored in FP64 afterwards), so the hardware reciprocal is accurate enough
             const float f = row[jr] * __builtin_amdgcn_rcpf(pr[jr]);
+            // live chunks in groups of NG: a group's broadcast reads issue together (one test
+            // per chunk makes each chunk wait for its own reads in turn)
 #pragma unroll
-            for (int cb = 0; cb < NC; ++cb) {
-              if (cb < NC - jb) {
-                const float4 p0 = pr4[2 * cb], p1 = pr4[2 * cb + 1];  // broadcast 16-byte reads
-                const int c = 8 * cb;
-                row[c + 0] = fmaf(-f, p0.x, row[c + 0]);
-                row[c + 1] = fmaf(-f, p0.y, row[c + 1]);
-                row[c + 2] = fmaf(-f, p0.z, row[c + 2]);
-                row[c + 3] = fmaf(-f, p0.w, row[c + 3]);
-                row[c + 4] = fmaf(-f, p1.x, row[c + 4]);
-                row[c + 5] = fmaf(-f, p1.y, row[c + 5]);
-                row[c + 6] = fmaf(-f, p1.z, row[c + 6]);
-                row[c + 7] = fmaf(-f, p1.w, row[c + 7]);
+            for (int g = 0; g < NC; g += NG) {
+              if (g < NC - jb) {
+                float4 pv[2 * NG];
+#pragma unroll
+                for (int u = 0; u < 2 * NG; ++u)
+                  if (2 * g + u < 2 * NC) pv[u] = pr4[2 * g + u];
+#pragma unroll
+                for (int u = 0; u < 2 * NG; ++u) {
+                  if (2 * g + u < 2 * NC) {
+                    const int c = 4 * (2 * g + u);
+                    row[c + 0] = fmaf(-f, pv[u].x, row[c + 0]);
+                    row[c + 1] = fmaf(-f, pv[u].y, row[c + 1]);
+                    row[c + 2] = fmaf(-f, pv[u].z, row[c + 2]);
+                    row[c + 3] = fmaf(-f, pv[u].w, row[c + 3]);
+                  }
+                }
               }
             }
           }
