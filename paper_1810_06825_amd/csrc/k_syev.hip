@@ -570,6 +570,7 @@ __global__ __launch_bounds__(kT) void syev_vectors_kernel(int n, double* d_out, 
       const double lam = mu[g];
       // stationary transform top-down: s_i into z
       double s = -lam;
+#pragma unroll 8
       for (int i = o; i < last; ++i) {
         z[i * kS] = s;
         const double dp = guard(Dr[i] + s, pivmin);
@@ -580,6 +581,7 @@ __global__ __launch_bounds__(kT) void syev_vectors_kernel(int n, double* d_out, 
       double p = Dr[last] - lam;
       int r = last;
       double gbest = fabs(z[last * kS] + p + lam);
+#pragma unroll 8
       for (int i = last - 1; i >= o; --i) {
         const double dm = guard(LLD[i] + p, pivmin);
         const double t = Dr[i] * rcp2(dm);
@@ -594,6 +596,7 @@ __global__ __launch_bounds__(kT) void syev_vectors_kernel(int n, double* d_out, 
       }
       // L+_i above r, top-down again
       s = -lam;
+#pragma unroll 8
       for (int i = o; i < r; ++i) {
         const double dp = guard(Dr[i] + s, pivmin);
         const double lp = Dr[i] * Lr[i] * rcp2(dp);
@@ -603,6 +606,7 @@ __global__ __launch_bounds__(kT) void syev_vectors_kernel(int n, double* d_out, 
       double u = (r < last) ? z[r * kS] : 0.0;
       z[r * kS] = 1.0;
       double zj = 1.0, nrm = 1.0;
+#pragma unroll 8
       for (int i = r; i < last; ++i) {
         const double unext = (i + 1 < last) ? z[(i + 1) * kS] : 0.0;
         zj = -u * zj;
@@ -611,6 +615,7 @@ __global__ __launch_bounds__(kT) void syev_vectors_kernel(int n, double* d_out, 
         u = unext;
       }
       zj = 1.0;
+#pragma unroll 8
       for (int i = r - 1; i >= o; --i) {
         zj = -z[i * kS] * zj;
         z[i * kS] = zj;
@@ -759,41 +764,74 @@ __global__ __launch_bounds__(kT) void syev_vectors_kernel(int n, double* d_out, 
   }
 
   // ---------------------------------------------------------------- 5. back-transformation
-  // Z into registers: wave w owns columns 8w..8w+7; lane L holds column 8w + L/8, rows
-  // 16 (L%8) .. 16 (L%8) + 15. The reflectors then move into the freed LDS matrix (row k holds
-  // v_k for rows k+1..n-1), and every wave applies all of them to its own columns with no
-  // further barrier: s = v^T z summed over the eight lanes of a column, z -= tau s v.
-  const int zc = 8 * wave + (lane >> 3), zr0 = 16 * (lane & 7);
-  double z[16];
+  // Z into registers: wave w < 8 owns columns 16w..16w+15; lane L holds columns
+  // 16w + 2 (L/8) and the next one, rows L%8 + 8q (q = 0..15). The eight lanes of a column
+  // pair read a reflector's entries from consecutive LDS words, and each entry read serves two
+  // columns (LDS return bandwidth bounds this phase). The reflectors move into the freed LDS
+  // matrix (row k holds v_k for rows k+1..n-1), and every wave applies all of them to its own
+  // columns with no further barrier: s = v^T z summed over the eight lanes of a column,
+  // z -= tau s v. Waves 8..15 have no columns here.
+  const int zc = 16 * wave + 2 * (lane >> 3), zr0 = lane & 7;
+  const bool zw = wave < 8;  // uniform per wave
+  double z0[16], z1[16];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) z[q] = (zr0 + q < n && zc < n) ? A[(zr0 + q) * kS + zc] : 0.0;
-  __syncthreads();
-  for (int idx = tid; idx < (n - 2) * kMaxL; idx += kT) {
-    const int k = idx / kMaxL, i = idx - k * kMaxL;
-    if (i < n - k - 1) A[k * kS + i] = house[idx];
+  for (int q = 0; q < 16; ++q) {
+    const int row = zr0 + 8 * q;
+    z0[q] = (zw && row < n && zc < n) ? A[row * kS + zc] : 0.0;
+    z1[q] = (zw && row < n && zc + 1 < n) ? A[row * kS + zc + 1] : 0.0;
   }
   __syncthreads();
-  for (int k = n - 3; k >= 0; --k) {
-    const double tk = tau[k];
-    if (tk == 0.0) continue;  // uniform
-    const double* hv = A + k * kS;
-    double vq[16];
-    double sp = 0.0;
+  if (n > 2) {  // uniform; with n <= 2 there are no reflectors
+    // a thread's loads are issued eight at a time before their LDS writes (indices clamped
+    // into the reflector block, so the loads need no branch), not one global round trip per
+    // element; eight keep the registers of Z and the staged values within budget
+    constexpr int kCopy = (kMaxL * kMaxL + kT - 1) / kT, kBatch = 8;
+    const int total = (n - 2) * kMaxL;
+#pragma unroll
+    for (int u0 = 0; u0 < kCopy; u0 += kBatch) {
+      double hv[kBatch];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) hv[u] = house[min(tid + (u0 + u) * kT, total - 1)];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const int idx = tid + (u0 + u) * kT;
+        const int k = idx / kMaxL, i = idx - k * kMaxL;
+        if (idx < total && i < n - k - 1) A[k * kS + i] = hv[u];
+      }
+    }
+  }
+  __syncthreads();
+  if (zw) {
+    for (int k = n - 3; k >= 0; --k) {
+      const double tk = tau[k];
+      if (tk == 0.0) continue;  // uniform
+      const double* hv = A + k * kS;
+      double vq[16];
+      double sa[2] = {0.0, 0.0}, sb[2] = {0.0, 0.0};  // two partial sums per column
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int row = zr0 + 8 * q;
+        vq[q] = (row >= k + 1 && row < n) ? hv[row - k - 1] : 0.0;
+        sa[q & 1] += vq[q] * z0[q];
+        sb[q & 1] += vq[q] * z1[q];
+      }
+      const double ta = tk * oct_allsum(sa[0] + sa[1]);
+      const double tb = tk * oct_allsum(sb[0] + sb[1]);
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        z0[q] -= ta * vq[q];
+        z1[q] -= tb * vq[q];
+      }
+    }
+    const int col0 = zc < n ? rank_s[zc] : 0, col1 = zc + 1 < n ? rank_s[zc + 1] : 0;
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-      const int row = zr0 + q;
-      vq[q] = (row >= k + 1 && row < n) ? hv[row - k - 1] : 0.0;
-      sp += vq[q] * z[q];
+      const int row = zr0 + 8 * q;
+      if (row < n) {
+        if (zc < n) W[(size_t)row * n + col0] = z0[q];
+        if (zc + 1 < n) W[(size_t)row * n + col1] = z1[q];
+      }
     }
-    const double ts = tk * oct_allsum(sp);
-#pragma unroll
-    for (int q = 0; q < 16; ++q) z[q] -= ts * vq[q];
-  }
-  if (zc < n) {
-    const int col = rank_s[zc];
-#pragma unroll
-    for (int q = 0; q < 16; ++q)
-      if (zr0 + q < n) W[(size_t)(zr0 + q) * n + col] = z[q];
   }
 }
 
