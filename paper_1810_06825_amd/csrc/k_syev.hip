@@ -192,11 +192,12 @@ __device__ __forceinline__ EigState eig_state(double* scratch) {
 // Phases 1 and 2.
 __global__ __launch_bounds__(kT) void syev_tridiag_kernel(const double* G, int ldg, int n, double* scratch) {
   __shared__ double A[kMaxL * kS];  // rows hold the reflectors v_k during the phase
-  __shared__ double d[kMaxL], e[kMaxL], e2[kMaxL], tau[kMaxL], pw[kMaxL];
+  __shared__ double d[kMaxL], e[kMaxL], e2[kMaxL], tau[kMaxL];
+  __shared__ __align__(16) double pw[kMaxL];
   __shared__ double Dr[kMaxL], Lr[kMaxL], LLD[kMaxL];
   __shared__ double bsig[kMaxL], bgl[kMaxL], bgu[kMaxL], btn[kMaxL];
   __shared__ double red[kT / 64], red2[kT / 64];
-  __shared__ double colbuf[kMaxL];
+  __shared__ __align__(16) double colbuf[kMaxL];
   __shared__ int bstart[kMaxL], bsize[kMaxL], bbad[kMaxL];
   __shared__ int sh_int[4];
   __shared__ double sh_dbl[4];
@@ -256,11 +257,18 @@ __global__ __launch_bounds__(kT) void syev_tridiag_kernel(const double* G, int l
         tau[k] = tk;
         e[k] = beta;
       }
+      // the own four rows and four columns of the column come as 16-byte LDS reads shared by
+      // all four selects (a read per element sits in its own branch and waits alone)
+      const double2 r01 = *reinterpret_cast<const double2*>(colbuf + 4 * rb);
+      const double2 r23 = *reinterpret_cast<const double2*>(colbuf + 4 * rb + 2);
+      const double2 c01 = *reinterpret_cast<const double2*>(colbuf + 4 * cb);
+      const double2 c23 = *reinterpret_cast<const double2*>(colbuf + 4 * cb + 2);
+      const double xr[4] = {r01.x, r01.y, r23.x, r23.y}, xc[4] = {c01.x, c01.y, c23.x, c23.y};
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
         const int R = 4 * rb + a, C = 4 * cb + a;
-        vr[a] = (R == k + 1) ? 1.0 : ((R > k + 1 && R < n) ? colbuf[R] * scal : 0.0);
-        vc[a] = (C == k + 1) ? 1.0 : ((C > k + 1 && C < n) ? colbuf[C] * scal : 0.0);
+        vr[a] = (R == k + 1) ? 1.0 : ((R > k + 1 && R < n) ? xr[a] * scal : 0.0);
+        vc[a] = (C == k + 1) ? 1.0 : ((C > k + 1 && C < n) ? xc[a] * scal : 0.0);
       }
       // v_k is kept in row k of the LDS matrix, which is free during this phase (a global
       // store here would make every barrier wait for it)
@@ -305,11 +313,16 @@ __global__ __launch_bounds__(kT) void syev_tridiag_kernel(const double* G, int l
       for (int w = 0; w < kT / 64; ++w) pv += red2[w];
       K *= 0.5 * pv;
       double wr[4], wc[4];
+      const double2 p01 = *reinterpret_cast<const double2*>(pw + 4 * rb);
+      const double2 p23 = *reinterpret_cast<const double2*>(pw + 4 * rb + 2);
+      const double2 q01 = *reinterpret_cast<const double2*>(pw + 4 * cb);
+      const double2 q23 = *reinterpret_cast<const double2*>(pw + 4 * cb + 2);
+      const double pr4[4] = {p01.x, p01.y, p23.x, p23.y}, pc4[4] = {q01.x, q01.y, q23.x, q23.y};
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
         const int R = 4 * rb + a, C = 4 * cb + a;
-        wr[a] = (R >= k + 1 && R < n) ? pw[R] - K * vr[a] : 0.0;
-        wc[a] = (C >= k + 1 && C < n) ? pw[C] - K * vc[a] : 0.0;
+        wr[a] = (R >= k + 1 && R < n) ? pr4[a] - K * vr[a] : 0.0;
+        wc[a] = (C >= k + 1 && C < n) ? pc4[a] - K * vc[a] : 0.0;
       }
 #pragma unroll
       for (int a = 0; a < 4; ++a)
