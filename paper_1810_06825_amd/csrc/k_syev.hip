@@ -688,6 +688,7 @@ __global__ __launch_bounds__(kT) void syev_vectors_kernel(int n, double* d_out, 
         const int sl = slot_s[g];
         double* lp = (sl < kLdsSlots) ? lds_lp + sl * kMaxL : lwork + (size_t)g * kMaxL;
         double s = -lam, yprev = 0.0, lprev = 0.0;
+#pragma unroll 8
         for (int i = o; i <= last; ++i) {
           const double dp = guard(Dr[i] + s, pfl);
           const double rp = rcp2(dp);
@@ -719,10 +720,12 @@ __global__ __launch_bounds__(kT) void syev_vectors_kernel(int n, double* d_out, 
         }
         if (nrm > 0.0 && nrm <= 1e300) {
           const double inv = 1.0 / sqrt(nrm);
+#pragma unroll 8
           for (int i = o; i <= last; ++i) z[i * kS] *= inv;
         } else if (ymax > 0.0) {  // sum of squares out of range: scale by the largest entry first
           const double sc = 1.0 / ymax;
           double nrm2 = 0.0;
+#pragma unroll 8
           for (int i = o; i <= last; ++i) {
             const double y = z[i * kS] * sc;
             z[i * kS] = y;
