@@ -57,6 +57,17 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
   return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
+// 1/v from the hardware reciprocal refined by two Newton steps (within a few ulps of the IEEE
+// quotient): it sits on the serial chain of every elimination step, where the IEEE division
+// sequence is several times longer. The multipliers only shape the coefficient matrix, whose
+// range is what the basis needs.
+__device__ __forceinline__ double recip_nr(double v) {
+  double r = __builtin_amdgcn_rcp(v);
+  r = fma(fma(-v, r, 1.0), r, r);
+  r = fma(fma(-v, r, 1.0), r, r);
+  return r;
+}
+
 struct SelectArgs {
   const float* X;
   int ldx;
@@ -271,6 +282,7 @@ __global__ __launch_bounds__(kFT) void lu_factor_kernel(const float* X, int ldx,
   __shared__ int colpos[kMaxL];
   __shared__ int colid[kMaxL];
   __shared__ int selrow[kMaxL];
+  __shared__ double dinv[kMaxL];  // 1 / U[s][s], formed once for the inversion
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int r = *cnt_p;
   if (t < kMaxL) colpos[t] = -1;
@@ -294,7 +306,7 @@ __global__ __launch_bounds__(kFT) void lu_factor_kernel(const float* X, int ldx,
   // multipliers of step s from column s's values colv (this lane's two rows) by its owner
   auto publish = [&](int s, const double (&colv)[2]) {
     const double mine = (s & 1) ? colv[1] : colv[0];
-    const double rp = 1.0 / readlane_d(mine, s >> 1);
+    const double rp = recip_nr(readlane_d(mine, s >> 1));
     double2 m;
     m.x = 2 * lane > s ? colv[0] * rp : 0.0;
     m.y = 2 * lane + 1 > s ? colv[1] * rp : 0.0;
@@ -352,6 +364,8 @@ __global__ __launch_bounds__(kFT) void lu_factor_kernel(const float* X, int ldx,
     });
   });
   __syncthreads();
+  if (t < r) dinv[t] = 1.0 / M[t * kMS + t];
+  __syncthreads();
   double tt[2][kFC];
   static_for<0, 2>([&](auto ic) {
     static_for<0, kFC>([&](auto cc) {
@@ -362,7 +376,7 @@ __global__ __launch_bounds__(kFT) void lu_factor_kernel(const float* X, int ldx,
   // columns cb .. cb + 7 of U^-1 are zero above... below row cb + 7: steps s > cb + 7 leave them alone
 #pragma unroll 1
   for (int s = min(r - 1, cb + kFC - 1); s >= 0; --s) {
-    const double rinv = 1.0 / M[s * kMS + s];
+    const double rinv = dinv[s];
     const double f0 = 2 * lane < s ? M[(2 * lane) * kMS + s] : 0.0;
     const double f1 = 2 * lane + 1 < s ? M[(2 * lane + 1) * kMS + s] : 0.0;
     const int pl = s >> 1;
