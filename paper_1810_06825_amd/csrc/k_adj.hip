@@ -159,9 +159,14 @@ __global__ __launch_bounds__(256) void sddmm4_kernel(const int32_t* rp, const in
           const int ce = __builtin_amdgcn_readlane(ci, (b + 2 * p) & 63);
           const int co = __builtin_amdgcn_readlane(ci, (b + 2 * p + 1) & 63);
           cs[p] = half ? co : ce;
-          q[p] = *reinterpret_cast<const float4*>(Q1 + (size_t)cs[p] * w + gc);
-          if (TWO) q2[p] = *reinterpret_cast<const float4*>(Q2 + (size_t)cs[p] * w + gc);
-          if (CORR) cv[p] = corr[cs[p]];
+          q[p] = q2[p] = make_float4(0.f, 0.f, 0.f, 0.f);
+          cv[p] = 0.f;
+          // pairs past the chunk's end are not gathered (the test is uniform over the wave)
+          if (b + 2 * p < nb) {
+            q[p] = *reinterpret_cast<const float4*>(Q1 + (size_t)cs[p] * w + gc);
+            if (TWO) q2[p] = *reinterpret_cast<const float4*>(Q2 + (size_t)cs[p] * w + gc);
+            if (CORR) cv[p] = corr[cs[p]];
+          }
         }
 #pragma unroll
         for (int p = 0; p < kSdPairs; ++p) {
