@@ -783,10 +783,10 @@ __global__ __launch_bounds__(kT) void syev_vectors_kernel(int n, double* d_out, 
   // Z into registers: wave w < 8 owns columns 16w..16w+15; lane L holds columns
   // 16w + 2 (L/8) and the next one, rows L%8 + 8q (q = 0..15). The eight lanes of a column
   // pair read a reflector's entries from consecutive LDS words, and each entry read serves two
-  // columns (LDS return bandwidth bounds this phase). The reflectors move into the freed LDS
-  // matrix (row k holds v_k for rows k+1..n-1), and every wave applies all of them to its own
-  // columns with no further barrier: s = v^T z summed over the eight lanes of a column,
-  // z -= tau s v. Waves 8..15 have no columns here.
+  // columns (half the LDS reads per reflector of one column per lane). The reflectors move
+  // into the freed LDS matrix (row k holds v_k for rows k+1..n-1), and every wave applies all
+  // of them to its own columns with no further barrier: s = v^T z summed over the eight lanes
+  // of a column, z -= tau s v. Waves 8..15 have no columns here.
   const int zc = 16 * wave + 2 * (lane >> 3), zr0 = lane & 7;
   const bool zw = wave < 8;  // uniform per wave
   double z0[16], z1[16];
