@@ -9,7 +9,7 @@ Pins (tests that tie each function to the paper or to mathematics, not to itself
 tests/test_oracle_*.py. Every function here is pinned; none is "parity unpinned".
 """
 from .adjoint import svd_adjoint_values  # noqa: F401
-from .frpca import check_args, frpca, frpca_alg5, frpcat, products, sign_convention  # noqa: F401
+from .frpca import check_args, frpca, pass_schedule, products, randomized_svd, sign_convention  # noqa: F401
 from .linalg import eig_asc, eigsvd, lu_pl  # noqa: F401
 from .philox import gaussian, philox4x32_10, uint32_stream  # noqa: F401
 from .sparse import csc_mirror, csr_matmul, csr_tmatmul, transpose  # noqa: F401

@@ -1,21 +1,28 @@
-"""FP64 frPCA (Alg. 5, m <= n) and frPCAt (Alg. 6, m >= n), step by step.
+"""FP64 frPCA (Alg. 5, m <= n) and frPCAt (Alg. 6, m >= n) of Section 3.3.
 
-The two algorithms are written out separately, each following its own listing in the
-paper's order and notation (Section 3.3). The pass parameter q (the number of passes over
-A, q >= 2) selects the start: for even q the sketch is one product with a Gaussian matrix
-followed by LU (q > 2) or eigSVD (q = 2); for odd q the Gaussian matrix itself is the
-starting basis (the modified power iteration of Section 3.2). floor((q-1)/2) power steps
-follow, each a product with A and A^T and an LU basis, the last one an eigSVD basis; a final
-eigSVD of the projected matrix gives the k leading triplets, taken in the order
-ind = k+s, k+s-1, ..., s+1 because eigSVD returns ascending singular values.
+What the method computes, for a sketch width l = k + s and q passes over A (q >= 2):
+
+* a starting basis of l columns on the short side of A: for odd q the Gaussian matrix
+  itself (the modified power iteration of Section 3.2, which saves one pass), for even q
+  the product of A with a Gaussian matrix drawn on the long side, reduced to a basis;
+* floor((q - 1) / 2) power steps, each applying A and A^T once and replacing the basis by
+  a basis of the result: the LU factor P^T L of Lemma 3 (eq. 8) in every step but the
+  last, eigSVD (Alg. 2) in the last one (and after the start when q = 2, where there is
+  no power step);
+* a Rayleigh-Ritz step: eigSVD of A applied to the final basis gives l singular triplets
+  in ascending order, of which the k largest are kept, largest first.
+
+Alg. 5 and Alg. 6 are the same computation with A and A^T exchanged (U and V swap
+roles), so one routine runs both on an operator whose rows are the long side.
 
 Readings where the paper is silent (each also applied by the GPU path):
   * centring (option): the PCA of data with rows as samples centres the columns; the
     products then act on A - 1 mu^T without forming it (see products());
   * orientation: m >= n runs Alg. 6, m < n runs Alg. 5 (the paper picks by shape and uses
     Alg. 6 on a square matrix in Section 4.2);
-  * the Gaussian draws come from Philox4x32-10 (see philox.py); Alg. 6's randn(k+s, m)
-    is drawn as its m x (k+s) transpose, element [r, j] = normal(r*(k+s) + j);
+  * the Gaussian draws come from Philox4x32-10 (see philox.py); the long-side draw of even
+    q is stored tall (rows of the long side, l columns), element [r, j] = normal(r*l + j),
+    which is the transpose of the paper's l x (long side) matrix;
   * rank guards (see linalg.py). Inner LU and eigSVD bases only guard against division by
     a numerically zero pivot or singular value (inner_tol, relative); the final eigSVD
     reports singular values <= rank_tol * max as exactly zero, with zero U and V columns.
@@ -77,77 +84,72 @@ def products(A, center: bool = False):
     return mul, tmul
 
 
-def frpcat(A, k: int, q: int, s: int, seed: int, rank_tol: float = 1e-5,
-           inner_tol: float = 1e-12, center: bool = False):
-    """Alg. 6 (frPCAt) for m >= n. Returns (U m x k, S k descending, V n x k)."""
-    mul, tmul = products(A, center)
-    l = k + s
+def pass_schedule(q: int):
+    """How q passes are spent (Section 3.3): returns (start, bases) where start is "gaussian"
+    (odd q: the Gaussian matrix is the first basis, no pass) or "sketch" (even q: one pass
+    with a long-side Gaussian matrix, followed by a basis), and bases lists the basis taken
+    after the start sketch (even q only) and after each power step, in order: "lu" or "eig".
+    Every power step costs two passes and the Rayleigh-Ritz step one."""
+    steps = (q - 1) // 2
     if q % 2 == 0:
-        omega_t = gaussian(seed, A.m, l)          # randn(k+s, m), stored transposed
-        Q = tmul(omega_t)                         # Q = (Omega A)^T
-        if q == 2:
-            Q = eigsvd(Q, inner_tol)[0]
-        else:
-            Q = lu_pl(Q, inner_tol)[0]
+        start = "sketch"
+        bases = ["eig" if steps == 0 else "lu"]
     else:
-        Q = gaussian(seed, A.n, l)                # Q = randn(n, k+s)
-    last = (q - 1) // 2
-    for i in range(1, last + 1):
-        X = tmul(mul(Q))                          # A^T (A Q)
-        if i == last:
-            Q = eigsvd(X, inner_tol)[0]
-        else:
-            Q = lu_pl(X, inner_tol)[0]
-    Uh, Sh, Vh, _ = eigsvd(mul(Q), rank_tol)
-    ind = np.arange(l - 1, s - 1, -1)             # k+s : -1 : s+1, zero-based
-    U = Uh[:, ind]
-    V = Q @ Vh[:, ind]
-    S = Sh[ind]
-    return U, S, V
+        start = "gaussian"
+        bases = []
+    bases += ["lu"] * max(steps - 1, 0) + (["eig"] if steps else [])
+    return start, bases
 
 
-def frpca_alg5(A, k: int, q: int, s: int, seed: int, rank_tol: float = 1e-5,
-               inner_tol: float = 1e-12, center: bool = False):
-    """Alg. 5 (frPCA) for m <= n. Returns (U m x k, S k descending, V n x k)."""
-    mul, tmul = products(A, center)
+def _basis(X: np.ndarray, kind: str, inner_tol: float) -> np.ndarray:
+    """A basis of range(X): the LU factor P^T L (Lemma 3) or the eigSVD left factor (Alg. 2)."""
+    return lu_pl(X, inner_tol)[0] if kind == "lu" else eigsvd(X, inner_tol)[0]
+
+
+def randomized_svd(fwd, back, long_rows: int, short_rows: int, k: int, q: int, s: int, seed: int,
+                   rank_tol: float = 1e-5, inner_tol: float = 1e-12, log=None):
+    """Rank-k SVD of an operator M (long_rows x short_rows, long_rows >= short_rows) given by
+    fwd: X -> M X and back: Y -> M^T Y, by the pass schedule of Section 3.3.
+
+    Returns (P long_rows x k, S k descending, R short_rows x k) with M ~ P diag(S) R^T.
+    log (optional) receives a line after each pass."""
+    say = log or (lambda msg: None)
     l = k + s
-    if q % 2 == 0:
-        Q = gaussian(seed, A.n, l)                # Q = randn(n, k+s)
-        Q = mul(Q)                                # Q = A Q
-        if q > 2:
-            Q = lu_pl(Q, inner_tol)[0]
-        else:
-            Q = eigsvd(Q, inner_tol)[0]
+    start, bases = pass_schedule(q)
+    todo = iter(bases)
+    if start == "sketch":
+        Q = _basis(back(gaussian(seed, long_rows, l)), next(todo), inner_tol)
+        say("start: sketch of the long-side Gaussian matrix and its basis")
     else:
-        Q = gaussian(seed, A.m, l)                # Q = randn(m, k+s)
-    last = (q - 1) // 2
-    for i in range(1, last + 1):
-        X = mul(tmul(Q))                          # A (A^T Q)
-        if i == last:
-            Q = eigsvd(X, inner_tol)[0]
-        else:
-            Q = lu_pl(X, inner_tol)[0]
-    Uh, Sh, Vh, _ = eigsvd(tmul(Q), rank_tol)
-    ind = np.arange(l - 1, s - 1, -1)
-    U = Q @ Vh[:, ind]
-    V = Uh[:, ind]
-    S = Sh[ind]
-    return U, S, V
+        Q = gaussian(seed, short_rows, l)
+        say("start: short-side Gaussian matrix")
+    for step, kind in enumerate(todo, 1):
+        Q = _basis(back(fwd(Q)), kind, inner_tol)
+        say(f"power step {step}: {kind} basis")
+    # Rayleigh-Ritz: eigSVD of M Q; eigSVD lists singular values ascending, so the k largest
+    # are its last k columns, taken largest first
+    W, sig, Z, _ = eigsvd(fwd(Q), rank_tol)
+    top = np.arange(l - 1, l - 1 - k, -1)
+    say("final eigSVD")
+    return W[:, top], sig[top], Q @ Z[:, top]
 
 
 def frpca(A, k: int, q: int, s: int, seed: int, rank_tol: float = 1e-5, inner_tol: float = 1e-12,
-          sign_fix: bool = True, center: bool = False):
+          sign_fix: bool = True, center: bool = False, log=None):
     """Rank-k truncated SVD of sparse A (or, with center, of A - 1 mu^T) by frPCA / frPCAt
     with q passes and oversampling s.
 
     Returns (U, S, V, info) with info = {"orientation": "alg6"|"alg5", "rank_dropped": r}.
     """
     check_args(A.m, A.n, k, q, s)
+    mul, tmul = products(A, center)
     if A.m >= A.n:
-        U, S, V = frpcat(A, k, q, s, seed, rank_tol, inner_tol, center)
+        # Alg. 6: the operator is A, its rows (the long side) carry U
+        U, S, V = randomized_svd(mul, tmul, A.m, A.n, k, q, s, seed, rank_tol, inner_tol, log)
         orient = "alg6"
     else:
-        U, S, V = frpca_alg5(A, k, q, s, seed, rank_tol, inner_tol, center)
+        # Alg. 5: the same schedule on A^T, whose rows carry V
+        V, S, U = randomized_svd(tmul, mul, A.n, A.m, k, q, s, seed, rank_tol, inner_tol, log)
         orient = "alg5"
     zero = S == 0.0
     U[:, zero] = 0.0

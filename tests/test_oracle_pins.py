@@ -215,15 +215,30 @@ def test_odd_passes_equal_subspace_iteration(q):
         assert sin_theta(Ur, U) < 1e-8 and sin_theta(Vr, V) < 1e-8
 
 
-@pytest.mark.parametrize("q", [2, 3, 4, 5])
-def test_orientation_swap_alg5_is_alg6_of_transpose(q):
-    A = _wide()
-    k, s, seed = 6, 3, 5
-    U5, S5, V5 = oracle.frpca_alg5(A, k, q, s, seed)
-    U6, S6, V6 = oracle.frpcat(oracle.transpose(A), k, q, s, seed)
-    np.testing.assert_allclose(S5, S6, rtol=1e-12)
-    np.testing.assert_allclose(np.abs(U5), np.abs(V6), atol=1e-10)
-    np.testing.assert_allclose(np.abs(V5), np.abs(U6), atol=1e-10)
+@pytest.mark.parametrize("q", [2, 3, 4, 5, 6, 7, 8])
+def test_pass_schedule_spends_exactly_q_passes(q):
+    """q is the number of passes over A (Section 3.3): counting the products the routine
+    makes gives q; LU bases come before the one eigSVD basis, and an even q starts with a
+    product of the long-side Gaussian matrix."""
+    D = np.random.default_rng(q).standard_normal((40, 25))
+    calls = []
+
+    def fwd(X):
+        calls.append("fwd")
+        return D @ X
+
+    def back(Y):
+        calls.append("back")
+        return D.T @ Y
+
+    oracle.randomized_svd(fwd, back, 40, 25, 4, q, 3, seed=1)
+    assert len(calls) == q
+    assert calls[0] == ("back" if q % 2 == 0 else "fwd")
+    assert calls[-1] == "fwd"
+    start, bases = oracle.pass_schedule(q)
+    assert start == ("sketch" if q % 2 == 0 else "gaussian")
+    assert bases.count("eig") == 1 and bases[-1] == "eig"
+    assert len(bases) == (q - 1) // 2 + (q % 2 == 0)
 
 
 @pytest.mark.parametrize("q", [2, 3, 5])
