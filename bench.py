@@ -1,14 +1,19 @@
 #!/usr/bin/env python
 """Benchmark of frPCA / frPCAt on one MI355X.
 
-Default workload: the 1,000,000 x 200,000 power-law CSR matrix (40 distinct nonzeros per row,
-Zipf(1.1) columns, lognormal(0,1) values), k = 100, s = 20, q = 5 passes, inputs resident in
-HBM. One step = one frpca_run (Gaussian draw, all passes, LU and eigSVD bases, final
-Rayleigh-Ritz, sign convention). Prints one JSON line on stdout; progress goes to stderr.
+Default workload: the Aminer-shaped CSR matrix (12,869,521 x 323,899, 20 distinct nonzeros per
+row, Zipf(1.0) columns, tf-idf values; the stand-in for the 12.87M x 324K matrix of Table 4),
+k = 100, s = 20, q = 5 passes, inputs resident in HBM. One step = one frpca_run (Gaussian draw,
+all passes, LU and eigSVD bases, final Rayleigh-Ritz, sign convention). Beside it: q = 3 and 7
+on the same matrix, the BF16-panel and FP32-Gram variants, the 1M x 200K power-law workload,
+the differentiated workload (500K x 100K, k = 50, q = 4) with its forward + backward time
+through the autograd function, and the FP64 CPU oracle on the whole headline job. Prints one
+JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -21,7 +26,10 @@ PEAK_HBM_GBPS = 8000.0       # MI355X HBM3E
 PEAK_FP64_TFLOPS = 78.6      # MI355X dense FP64 matrix
 PEAK_FP32_MFMA_TFLOPS = 157.3  # MI355X dense FP32 matrix
 SEED = 20181015
-PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic_spmm_zipf_lognormal.json")
+METRIC = "frPCA wall time (s) + SpMM HBM GB/s at k=100; fwd+bwd time vs fwd at stated error"
+# other pass counts timed beside the headline one, per workload
+PASS_SWEEP = {"aminer_tfidf": (3, 7), "zipf_lognormal": (4, 6), "planted_blocks": (3, 7), "zipf_normal": (2, 6)}
+SPMM_SOURCES = ("k_spmm.hip", "k_bcsc.hip")
 
 
 def log(*a):
@@ -33,10 +41,13 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=10)
     p.add_argument("--warmup", type=int, default=3)
-    p.add_argument("--workload", default="zipf_lognormal")
+    p.add_argument("--workload", default="aminer_tfidf")
     p.add_argument("--passes", type=int, default=0, help="override q")
-    p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--no-extras", action="store_true", help="skip the odd/even, BF16 and backward timings")
+    p.add_argument("--cpu-baseline", choices=("full", "none"), default="full",
+                   help="full: time the FP64 oracle on the whole headline job (minutes of host CPU)")
+    p.add_argument("--no-cpu-baseline", action="store_true", help="same as --cpu-baseline none")
+    p.add_argument("--no-extras", action="store_true",
+                   help="only the headline timing (profiling runs): no pass sweep, variants or other workloads")
     p.add_argument("--gram-f32", action="store_true",
                    help="time the variant whose eigSVD Gram runs on the FP32 matrix cores (profiling runs)")
     p.add_argument("--copy-calibration", action="store_true",
@@ -59,11 +70,40 @@ def copy_calibration():
     print(json.dumps({"copy_calibration": {"bytes_read": 4 * n, "bytes_written": 4 * n, "dispatches": 5}}), flush=True)
 
 
-def spmm_source_hash():
-    import hashlib
+def measured_copy_peak(torch) -> dict:
+    """Bytes moved per second by a device-to-device copy of 2 GiB (read + write), best of 10:
+    the practical streaming rate of this GPU's HBM beside the nominal 8 TB/s."""
+    n = 1 << 29
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(10):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del a, b
+    torch.cuda.empty_cache()
+    gbps = 2 * 4 * n / (best * 1e-3) / 1e9
+    return {"GBps": round(gbps, 1), "frac_of_nominal": round(gbps / PEAK_HBM_GBPS, 4),
+            "kernel": "torch copy_ of 2 GiB FP32 (2 GiB read + 2 GiB written), best of 10"}
 
-    with open(os.path.join(ROOT, "paper_1810_06825_amd", "csrc", "k_spmm.hip"), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+
+def spmm_source_hash():
+    h = hashlib.sha256()
+    for f in SPMM_SOURCES:
+        with open(os.path.join(ROOT, "paper_1810_06825_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_file(workload: str) -> str:
+    return os.path.join(ROOT, "profiles", f"traffic_spmm_{workload}.json")
 
 
 def slice_rows(A, m_s):
@@ -75,10 +115,29 @@ def slice_rows(A, m_s):
 
 
 def spmm_bytes(A, l, trans):
-    """Compulsory bytes of one product: nonzero indices + values, 32-bit pointers, the
-    input panel read once and the output panel written once (l columns of FP32)."""
+    """Compulsory bytes of one product: nonzero indices + values, 32-bit pointers of the
+    segments, the input panel read once and the output panel written once (l columns of FP32)."""
     nseg, nin = (A.n, A.m) if trans else (A.m, A.n)
     return A.nnz * 8 + (nseg + 1) * 4 + nin * l * 4 + nseg * l * 4
+
+
+def class_bytes(A, l, info) -> dict:
+    """Algorithmic bytes per launch of each sparse-product kernel class.
+
+    spmm_fwd: the forward product (A Q for m >= n). spmm_back: the back product, or with
+    frequent ("hot") columns its row-blocked part: their index/value pairs, the segment
+    pointers, Y read once and one partial row per (row block, hot column) written.
+    spmm_back_tail: the other columns: their pairs and pointers, Y read once (it touches
+    nearly every row), their rows of X written."""
+    a6 = A.m >= A.n
+    out = {"spmm_fwd": spmm_bytes(A, l, trans=not a6), "spmm_back": spmm_bytes(A, l, trans=a6)}
+    if a6 and info["hot_cols"] > 0:
+        nseg = info["row_blocks"] * info["hot_cols"]
+        out["spmm_back"] = info["hot_nnz"] * 8 + (nseg + 1) * 4 + A.m * l * 4 + nseg * l * 4
+        tail_cols = A.n - info["hot_cols"]
+        out["spmm_back_tail"] = ((A.nnz - info["hot_nnz"]) * 8 + (tail_cols + 1) * 4 + A.m * l * 4
+                                 + tail_cols * l * 4)
+    return out
 
 
 def timed_runs(mat, k, q, s, steps, warmup, torch):
@@ -100,101 +159,83 @@ def timed_runs(mat, k, q, s, steps, warmup, torch):
     return ev0.elapsed_time(ev1) / steps, (U, S, V)
 
 
-def main():
-    args = parse()
-    if args.copy_calibration:
-        copy_calibration()
-        return
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
-              "(the row-partitioned multi-GPU scheme is described, not implemented)", file=sys.stderr)
-        sys.exit(2)
-    import numpy as np
-    import torch
-
-    from paper_1810_06825_amd import FrPCA
-    from synth import WORKLOADS
-
-    gen, kw, k, s, q = WORKLOADS[args.workload]
-    if args.passes:
-        q = args.passes
-    l = k + s
-    t0 = time.time()
-    A = gen(**kw)
-    log(f"generated {args.workload} {A.m}x{A.n} nnz={A.nnz} in {time.time() - t0:.1f}s")
-    # the timed handle records no per-class events (the production configuration); a second
-    # handle with opts.timing gives the per-class breakdown of the same runs
-    mat = FrPCA.from_csr(A, device="cuda:0", gram_f32=args.gram_f32)
-    create_ms = mat.info()["create_ms"]
-    log(f"create (validation + column-major mirror) {create_ms:.1f} ms")
-
-    ms, (U, S, V) = timed_runs(mat, k, q, s, args.steps, args.warmup, torch)
-    log(f"frpca_run q={q}: {ms:.3f} ms/step")
-    matt = FrPCA.from_csr(A, device="cuda:0", timing=True, gram_f32=args.gram_f32)
-    ms_timers, _ = timed_runs(matt, k, q, s, args.steps, args.warmup, torch)
-    info = matt.info()
-    log(f"with per-class events: {ms_timers:.3f} ms/step")
+def per_class(info, steps) -> dict:
     per = {}
     for name in info["t_ms"]:
         c = info["t_count"][name]
         if c:
-            per[name] = {"ms_total_per_step": info["t_ms"][name] / args.steps, "launches_per_step": c / args.steps,
+            per[name] = {"ms_total_per_step": info["t_ms"][name] / steps, "launches_per_step": c / steps,
                          "ms_per_launch": info["t_ms"][name] / c}
-    log("per-class:", json.dumps({kk: round(v["ms_total_per_step"], 3) for kk, v in per.items()}))
+    return per
 
-    # dominant kernel and its roofline (algorithmic bytes / measured launch duration)
-    dom = max(per, key=lambda n: per[n]["ms_total_per_step"])
-    a6 = A.m >= A.n
-    fwd_bytes = spmm_bytes(A, l, trans=not a6)
-    back_bytes = spmm_bytes(A, l, trans=a6)
-    if a6 and info["hot_cols"] > 0:
-        # the back product runs as three kernels: the row-blocked hot part (index/value pairs,
-        # segment pointers, Y read once, one partial row per (row block, hot column) written),
-        # the tail columns (their pairs, pointers, gathered rows at most all of Y, rows out),
-        # and the fixed-order combine; the "spmm_back" class is the first
-        nseg = info["row_blocks"] * info["hot_cols"]
-        back_bytes = info["hot_nnz"] * 8 + (nseg + 1) * 4 + A.m * l * 4 + nseg * l * 4
-    roof = None
-    if dom in ("spmm_fwd", "spmm_back"):
-        b = fwd_bytes if dom == "spmm_fwd" else back_bytes
-        ach = b / (per[dom]["ms_per_launch"] * 1e-3) / 1e9
-        traffic = None
-        if os.path.exists(PROFILE_TRAFFIC):
-            # HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counter runs, valid only for
-            # the SpMM source they were taken on
-            with open(PROFILE_TRAFFIC) as f:
-                tr = json.load(f)
-            if (tr.get("kernel_source_sha256") == spmm_source_hash() and dom in tr.get("per_launch", {})
-                    and tr.get("workload", "").startswith(args.workload + " ")):
-                traffic = tr["per_launch"][dom]["hbm_bytes"]
-        roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
-                "frac": round(ach / PEAK_HBM_GBPS, 4), "traffic": traffic,
-                "algorithmic_bytes_per_launch": b}
+
+def sin_theta(Ref, X):
+    import numpy as np
+
+    Q = np.linalg.qr(X)[0]
+    Qr = np.linalg.qr(Ref)[0]
+    return float(np.linalg.norm(Q - Qr @ (Qr.T @ Q), 2))
+
+
+def free(torch, *objs):
+    for o in objs:
+        if hasattr(o, "close"):
+            o.close()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+def headline(args, A, k, q, s, torch, np):
+    """Time frpca_run on A; per-class breakdown, roofline of the dominant kernel, Gram figures."""
+    from paper_1810_06825_amd import FrPCA
+
+    l = k + s
+    mat = FrPCA.from_csr(A, device="cuda:0", gram_f32=args.gram_f32)
+    create_ms = mat.info()["create_ms"]
+    log(f"create (validation + column-major mirror + row-blocked order) {create_ms:.1f} ms")
+    ms, (U, S, V) = timed_runs(mat, k, q, s, args.steps, args.warmup, torch)
+    log(f"frpca_run q={q}: {ms:.3f} ms/step")
+    # a second handle records per-class HIP events on the library's stream
+    matt = FrPCA.from_csr(A, device="cuda:0", timing=True, gram_f32=args.gram_f32)
+    ms_timers, _ = timed_runs(matt, k, q, s, args.steps, args.warmup, torch)
+    info = matt.info()
+    per = per_class(info, args.steps)
+    log(f"with per-class events: {ms_timers:.3f} ms/step;",
+        json.dumps({kk: round(v["ms_total_per_step"], 3) for kk, v in per.items()}))
+    cb = class_bytes(A, l, info)
     spmm_report = {}
-    for name, b in (("spmm_fwd", fwd_bytes), ("spmm_back", back_bytes)):
+    for name, b in cb.items():
         if name in per:
             t = per[name]["ms_per_launch"] * 1e-3
-            nseg = A.m if (name == "spmm_fwd") == a6 else A.n   # segments = rows of A for the CSR side
-            gathered = A.nnz * (8 + l * 4) + nseg * l * 4
             spmm_report[name] = {"ms_per_launch": round(per[name]["ms_per_launch"], 4),
-                                 "algorithmic_GBps": round(b / t / 1e9, 1),
-                                 "per_nnz_gather_GBps": round(gathered / t / 1e9, 1)}
-    if "spmm_combine" in per:
-        c = per["spmm_combine"]
-        tail = per.get("spmm_back_tail", {"ms_per_launch": 0.0})
-        spmm_report["spmm_back"]["tail_ms_per_launch"] = round(tail["ms_per_launch"], 4)
-        spmm_report["spmm_back"]["combine_ms_per_launch"] = round(c["ms_per_launch"], 4)
-        spmm_report["spmm_back"]["hot_cols"] = info["hot_cols"]
-        spmm_report["spmm_back"]["hot_nnz"] = info["hot_nnz"]
-        spmm_report["spmm_back"]["row_blocks"] = info["row_blocks"]
-        # the whole transpose product against its compulsory bytes (index/value pairs, CSC
-        # pointers, Y read once, X written once)
-        whole = per["spmm_back"]["ms_per_launch"] + tail["ms_per_launch"] + c["ms_per_launch"]
-        spmm_report["spmm_back"]["product_ms"] = round(whole, 4)
-        spmm_report["spmm_back"]["product_compulsory_GBps"] = round(spmm_bytes(A, l, trans=True) / (whole * 1e-3) / 1e9, 1)
+                                 "algorithmic_bytes": b, "algorithmic_GBps": round(b / t / 1e9, 1),
+                                 "frac_of_hbm_peak": round(b / t / 1e9 / PEAK_HBM_GBPS, 4)}
+    if A.m >= A.n and "spmm_combine" in per:
+        whole = sum(per.get(c, {"ms_per_launch": 0.0})["ms_per_launch"]
+                    for c in ("spmm_back", "spmm_back_tail", "spmm_combine"))
+        spmm_report["back_product"] = {
+            "ms": round(whole, 4), "hot_cols": info["hot_cols"], "hot_nnz": info["hot_nnz"],
+            "row_blocks": info["row_blocks"],
+            "compulsory_GBps": round(spmm_bytes(A, l, trans=True) / (whole * 1e-3) / 1e9, 1)}
+    # dominant sparse-product kernel class and its roofline: algorithmic bytes per launch over
+    # the launch's average duration from the events above
+    sp = [c for c in per if c in cb]
+    dom = max(sp, key=lambda c: per[c]["ms_total_per_step"])
+    ach = cb[dom] / (per[dom]["ms_per_launch"] * 1e-3) / 1e9
+    traffic = None
+    tf = traffic_file(args.workload)
+    if os.path.exists(tf):
+        # FETCH_SIZE / WRITE_SIZE bytes per launch, valid only for the kernel sources and the
+        # workload the counters were taken on
+        with open(tf) as f:
+            tr = json.load(f)
+        if tr.get("kernel_source_sha256") == spmm_source_hash() and dom in tr.get("per_launch", {}):
+            traffic = tr["per_launch"][dom]["fetch_write_bytes"]
+    roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+            "frac": round(ach / PEAK_HBM_GBPS, 4), "traffic": traffic, "algorithmic_bytes_per_launch": cb[dom]}
     gram = None
     if "gram" in per:
-        # two Gram launches per run (the short-side panel of the one inner eigSVD basis and the
+        # two Gram launches per run (the short-side panel of the last inner eigSVD basis and the
         # long-side panel Z of the final step), each with its reduction. Algorithmic flops: the
         # l (l + 1) / 2 distinct entries of the symmetric product, 2 per row each. Executed: the
         # upper 16 x 16 tiles of l padded to an even tile count, as issued on the matrix cores.
@@ -208,110 +249,227 @@ def main():
         gram = {"mfma": "fp32" if args.gram_f32 else "fp64", "ms_per_run": round(t_g * 1e3, 4),
                 "algorithmic_tflops": round(alg, 2), "executed_tflops": round(exe, 2), "peak_tflops": peak,
                 "frac_algorithmic": round(alg / peak, 4), "frac_executed": round(exe / peak, 4)}
+    matt.close()
+    res = {"ms": ms, "create_ms": create_ms, "per": per, "roofline": roof, "spmm": spmm_report, "gram": gram,
+           "ms_timers": ms_timers, "factors": (U, S, V)}
+    return mat, res
 
+
+def variants(A, k, q, s, steps, torch, np, S_ref):
+    """BF16 panels, the FP32-MFMA Gram and the centred run on the headline matrix: time and
+    singular-value difference against the default FP32 path."""
+    from paper_1810_06825_amd import FrPCA
+
+    out = {}
+    Sf = S_ref.double().cpu().numpy()
+    n = max(3, steps // 2)
+    for name, kw in (("bf16_panel", {"panel_bf16": True}), ("gram_f32", {"gram_f32": True}),
+                     ("centered", {"center": True})):
+        m2 = FrPCA.from_csr(A, device="cuda:0", **kw)
+        t, (_, S2, _) = timed_runs(m2, k, q, s, n, 1, torch)
+        m2.close()
+        m2 = FrPCA.from_csr(A, device="cuda:0", timing=True, **kw)
+        timed_runs(m2, k, q, s, n, 1, torch)
+        inf = m2.info()
+        m2.close()
+        rec = {"ms": round(t, 3)}
+        if name != "centered":   # the centred run computes another matrix's spectrum
+            rec["sigma_rel_diff_vs_fp32"] = float(np.max(np.abs(S2.double().cpu().numpy() - Sf) / Sf))
+            rec["S"] = S2.double().cpu().numpy()
+        if name == "gram_f32":
+            rec["gram_ms"] = round(inf["t_ms"]["gram"] / n, 4)
+        if name == "centered":
+            rec["rank1_terms_ms"] = round(inf["t_ms"]["center"] / n, 4)
+        log(f"variant {name}: {t:.3f} ms", {kk: v for kk, v in rec.items() if kk != "S"})
+        out[name] = rec
+        torch.cuda.empty_cache()
+    return out
+
+
+def secondary_zipf(args, torch, np):
+    """The 1,000,000 x 200,000 power-law workload (Zipf 1.1 columns, 40 per row, lognormal
+    values), k = 100, s = 20, q = 5 (also 4 and 6)."""
+    from paper_1810_06825_amd import FrPCA
+    from synth import WORKLOADS
+
+    gen, kw, k, s, q = WORKLOADS["zipf_lognormal"]
+    A = gen(**kw)
+    l = k + s
+    mat = FrPCA.from_csr(A, device="cuda:0")
+    ms, _ = timed_runs(mat, k, q, s, args.steps, args.warmup, torch)
+    rec = {"workload": f"zipf_lognormal {A.m}x{A.n} CSR, {A.nnz} nnz", "k": k, "s": s, "ms_q5": round(ms, 3)}
+    for qq in (4, 6):
+        t, _ = timed_runs(mat, k, qq, s, max(3, args.steps // 2), 1, torch)
+        rec[f"ms_q{qq}"] = round(t, 3)
+    mat.close()
+    matt = FrPCA.from_csr(A, device="cuda:0", timing=True)
+    timed_runs(matt, k, q, s, max(3, args.steps // 2), 1, torch)
+    info = matt.info()
+    per = per_class(info, max(3, args.steps // 2))
+    matt.close()
+    cb = class_bytes(A, l, info)
+    rec["spmm_GBps"] = {c: round(cb[c] / (per[c]["ms_per_launch"] * 1e-3) / 1e9, 1) for c in cb if c in per}
+    rec["per_class_ms"] = {kk: round(v["ms_total_per_step"], 4) for kk, v in per.items()}
+    log("zipf_lognormal:", json.dumps(rec))
+    free(torch)
+    return rec
+
+
+def differentiated(args, torch, np):
+    """The differentiated workload: 500,000 x 100,000, 30 per row, Zipf 1.1, N(0,1) values,
+    k = 50, s = 10, q = 4, loss = sum(sigma) + ||U W||^2 (W 50 x 8, seed 7). Forward alone
+    (frpca_run) against forward + loss + backward through the autograd function, with the
+    forward's error against the FP64 oracle and the gradient's against its closed form (the
+    second loss term is invariant, so dL/dA = sum_i u_i v_i^T at the stored nonzeros)."""
+    import oracle
+    from paper_1810_06825_amd import FrPCA, frpca_autograd
+    from synth import WORKLOADS
+
+    gen, kw, k, s, q = WORKLOADS["zipf_normal"]
+    A = gen(**kw)
+    mat = FrPCA.from_csr(A, device="cuda:0")
+    nrep = max(3, args.steps)
+    ms_f, (U, S, V) = timed_runs(mat, k, q, s, nrep, 2, torch)
+    vals = torch.from_numpy(A.val).to("cuda:0")
+    W = torch.from_numpy(np.random.default_rng(7).standard_normal((k, 8)).astype(np.float32)).to("cuda:0")
+
+    def step():
+        v = vals.detach().requires_grad_(True)
+        U_, S_, V_ = frpca_autograd(v, mat, k, q, s, SEED)
+        loss = S_.sum() + ((U_ @ W) ** 2).sum()
+        loss.backward()
+        return U_, S_, V_, v.grad
+
+    for _ in range(2):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(nrep):
+        Ua, Sa, Va, g = step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_fb = e0.elapsed_time(e1) / nrep
+    # backward alone, by kernel class, on a handle with events
+    matt = FrPCA.from_csr(A, device="cuda:0", timing=True)
+    matt.run(k, q, s, SEED)
+    dU = 2.0 * (Ua @ W) @ W.T
+    matt.reset_timers()
+    for _ in range(nrep):
+        matt.backward(dU, torch.ones_like(Sa), None)
+    torch.cuda.synchronize()
+    binf = matt.info()
+    matt.close()
+    Ug, Sg, Vg, gg = (t.detach().double().cpu().numpy() for t in (Ua, Sa, Va, g))
+    mat.close()
+    log("differentiated: oracle forward (FP64, CPU)")
+    Uo, So, Vo, _ = oracle.frpca(A, k + 1, q, s - 1, SEED)
+    sig_err = float(np.max(np.abs(Sg - So[:k]) / So[:k]))
+    sin_v = sin_theta(Vo[:, :k], Vg)
+    rows = np.repeat(np.arange(A.m), np.diff(A.row_ptr))
+    ref = np.empty(A.nnz)
+    for e0_ in range(0, A.nnz, 1 << 21):
+        e1_ = min(A.nnz, e0_ + (1 << 21))
+        ref[e0_:e1_] = np.einsum("ij,ij->i", Ug[rows[e0_:e1_]], Vg[A.col[e0_:e1_]])
+    grad_err = float(np.abs(gg - ref).max() / np.abs(ref).max())
+    rec = {"workload": f"zipf_normal {A.m}x{A.n} CSR, {A.nnz} nnz", "k": k, "s": s, "passes": q,
+           "loss": "sum(sigma) + ||U W||^2, W 50x8 N(0,1) seed 7",
+           "ms_forward": round(ms_f, 3), "ms_forward_backward": round(ms_fb, 3),
+           "fwd_bwd_over_fwd": round(ms_fb / ms_f, 3),
+           "backward_per_class_ms": {kk: round(binf["t_ms"][kk] / nrep, 4) for kk in binf["t_ms"]
+                                     if binf["t_count"][kk]},
+           "error": {"sigma_rel_err_vs_oracle": sig_err, "sin_theta_V_vs_oracle": sin_v,
+                     "grad_rel_err_vs_closed_form": grad_err}}
+    log("differentiated:", json.dumps(rec))
+    free(torch)
+    return rec
+
+
+def cpu_baseline_full(A, k, q, s, factors, np):
+    """The FP64 oracle on the whole headline job, timed on the host, and the GPU's error
+    against it (singular values, and the subspace of V)."""
+    import oracle
+    from threadpoolctl import threadpool_info
+
+    t0 = time.time()
+    Uo, So, Vo, _ = oracle.frpca(A, k + 1, q, s - 1, SEED,
+                                 log=lambda msg: log(f"  oracle {msg} ({time.time() - t0:.0f} s)"))
+    tcpu = time.time() - t0
+    cores = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    _, S, V = factors
+    Sg = S.double().cpu().numpy()
+    Vg = V.double().cpu().numpy()
+    sig_err = float(np.max(np.abs(Sg - So[:k]) / So[:k]))
+    sin_v = sin_theta(Vo[:, :k], Vg)
+    try:
+        import psutil
+
+        mem_gb = round(psutil.virtual_memory().total / 2 ** 30, 1)
+    except Exception:
+        mem_gb = None
+    log(f"oracle on the whole job: {tcpu:.1f} s; GPU sigma err {sig_err:.2e}, sin theta V {sin_v:.2e}")
+    return ({"value": round(tcpu, 2), "unit": "s", "cores": int(cores), "kind": "oracle",
+             "sample": (f"the whole job: {A.m}x{A.n}, {A.nnz} nnz, k={k}, s={s}, q={q}, seed {SEED}, one run "
+                        f"(FP64 numpy/scipy; dense steps on {cores} BLAS threads, scipy's sparse products on one "
+                        f"thread; host memory {mem_gb} GiB)"),
+             "gpu_vs_oracle": {"sigma_rel_err": sig_err, "sin_theta_V": sin_v}}, So[:k])
+
+
+def main():
+    args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
+              "(the row-partitioned multi-GPU scheme is described, not implemented)", file=sys.stderr)
+        sys.exit(2)
+    if args.no_cpu_baseline:
+        args.cpu_baseline = "none"
+    import numpy as np
+    import torch
+
+    from synth import WORKLOADS
+
+    gen, kw, k, s, q = WORKLOADS[args.workload]
+    if args.passes:
+        q = args.passes
+    copy_peak = None if args.no_extras else measured_copy_peak(torch)
+    if copy_peak:
+        log("device copy:", copy_peak)
+    t0 = time.time()
+    A = gen(**kw)
+    log(f"generated {args.workload} {A.m}x{A.n} nnz={A.nnz} in {time.time() - t0:.1f}s")
+    mat, h = headline(args, A, k, q, s, torch, np)
+    ms = h["ms"]
     extras = {}
+    var = {}
     if not args.no_extras:
-        for qq in sorted({4, 6, q} - {q}):
-            m2, _ = timed_runs(mat, k, qq, s, max(3, args.steps // 2), 1, torch)
-            extras[f"ms_q{qq}"] = round(m2, 3)
-            log(f"q={qq}: {m2:.3f} ms")
-        # differentiated form: loss = sum(sigma) + ||U W||^2 (W: k x 8, seeded). A backward uses
-        # the factors of its handle's last run: both handles run q once more first. Its time
-        # comes from the handle without per-class events, the breakdown from the other.
-        U, S, V = mat.run(k, q, s, SEED)
-        matt.run(k, q, s, SEED)
-        W = torch.from_numpy(np.random.default_rng(7).standard_normal((k, 8)).astype(np.float32)).cuda()
-        dU = 2.0 * (U @ W) @ W.T
-        dS = torch.ones_like(S)
-        nb = max(3, args.steps // 2)
-        for _ in range(2):
-            mat.backward(U, S, V, dU, dS, None)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(nb):
-            mat.backward(U, S, V, dU, dS, None)
-        e1.record()
-        torch.cuda.synchronize()
-        bms = e0.elapsed_time(e1) / nb
-        matt.reset_timers()
-        for _ in range(nb):
-            matt.backward(U, S, V, dU, dS, None)
-        torch.cuda.synchronize()
-        binf = matt.info()
-        extras["backward_per_class_ms"] = {kk: round(binf["t_ms"][kk] / nb, 4) for kk in binf["t_ms"]
-                                           if binf["t_count"][kk]}
-        extras["ms_backward"] = round(bms, 3)
-        extras["fwd_bwd_over_fwd"] = round((ms + bms) / ms, 3)
-        log(f"backward {bms:.3f} ms, (fwd+bwd)/fwd = {(ms + bms) / ms:.3f}")
-        mat_b = FrPCA.from_csr(A, device="cuda:0", panel_bf16=True)
-        mb, (Ub, Sb, Vb) = timed_runs(mat_b, k, q, s, max(3, args.steps // 2), 1, torch)
-        Sf = S.double().cpu().numpy()
-        extras["ms_bf16_panel"] = round(mb, 3)
-        extras["bf16_sigma_rel_diff_vs_fp32"] = float(np.max(np.abs(Sb.double().cpu().numpy() - Sf) / Sf))
-        log(f"BF16 panels: {mb:.3f} ms, sigma rel diff vs FP32 {extras['bf16_sigma_rel_diff_vs_fp32']:.2e}")
-        mat_b.close()
-        # eigSVD's Gram on the FP32 matrix cores (16-row FP32 sums added in FP64): time and
-        # singular-value difference against the default FP64-MFMA Gram
-        ng = max(3, args.steps // 2)
-        mat_g = FrPCA.from_csr(A, device="cuda:0", gram_f32=True)
-        mg, (_, Sg32, _) = timed_runs(mat_g, k, q, s, ng, 1, torch)
-        mat_g.close()
-        mat_g = FrPCA.from_csr(A, device="cuda:0", gram_f32=True, timing=True)
-        timed_runs(mat_g, k, q, s, ng, 1, torch)
-        ginf = mat_g.info()
-        extras["ms_gram_f32"] = round(mg, 3)
-        extras["gram_f32_gram_ms"] = round(ginf["t_ms"]["gram"] / ng, 4)
-        extras["gram_f32_sigma_rel_diff_vs_fp64_gram"] = float(
-            np.max(np.abs(Sg32.double().cpu().numpy() - Sf) / Sf))
-        log(f"FP32-MFMA Gram: {mg:.3f} ms (Gram {extras['gram_f32_gram_ms']:.3f} ms), sigma rel diff vs FP64 Gram "
-            f"{extras['gram_f32_sigma_rel_diff_vs_fp64_gram']:.2e}")
-        mat_g.close()
-        # centred PCA (A - 1 mu^T, never formed): cost of the rank-1 terms
-        mat_c = FrPCA.from_csr(A, device="cuda:0", center=True)
-        mc, _ = timed_runs(mat_c, k, q, s, max(3, args.steps // 2), 1, torch)
-        mat_c.close()
-        mat_c = FrPCA.from_csr(A, device="cuda:0", center=True, timing=True)
-        timed_runs(mat_c, k, q, s, max(3, args.steps // 2), 1, torch)
-        cinf = mat_c.info()
-        extras["ms_centered"] = round(mc, 3)
-        extras["centered_terms_ms"] = round(cinf["t_ms"]["center"] / max(3, args.steps // 2), 4)
-        log(f"centred: {mc:.3f} ms (rank-1 terms {extras['centered_terms_ms']:.3f} ms)")
-        mat_c.close()
-
+        for qq in PASS_SWEEP.get(args.workload, ()):
+            t, _ = timed_runs(mat, k, qq, s, max(3, args.steps // 2), 1, torch)
+            extras[f"ms_q{qq}"] = round(t, 3)
+            log(f"q={qq}: {t:.3f} ms")
+        var = variants(A, k, q, s, args.steps, torch, np, h["factors"][1])
+    U, S, V = (t.detach() for t in h["factors"])
+    S_host, V_host = S.cpu(), V.cpu()
+    mat.close()
+    del U, S, V, h["factors"]
+    free(torch)
+    secondary = diff = None
+    if not args.no_extras:
+        secondary = secondary_zipf(args, torch, np)
+        diff = differentiated(args, torch, np)
     cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
-        from threadpoolctl import threadpool_info
-
-        m_s = max(A.m // 4, min(A.m, A.n + 1))
-        As = slice_rows(A, m_s)
-        t1 = time.perf_counter()
-        Uo, So, Vo, _ = oracle.frpca(As, k, q, s, SEED)
-        tcpu = time.perf_counter() - t1
-        cores = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
-        scale = A.nnz / As.nnz
-        # GPU on the same sample: error of the FP32 path against the FP64 oracle
-        ms_s = FrPCA.from_csr(As, device="cuda:0")
-        Ug, Sg, Vg = (t.double().cpu().numpy() for t in ms_s.run(k, q, s, SEED))
-        ms_s.close()
-        sig_err = float(np.max(np.abs(Sg - So) / So))
-        Qo = np.linalg.qr(Vo)[0]
-        sin_v = float(np.linalg.norm(Vg - Qo @ (Qo.T @ Vg), 2))
-        ms_s = FrPCA.from_csr(As, device="cuda:0", gram_f32=True)
-        Sg32 = ms_s.run(k, q, s, SEED)[1].double().cpu().numpy()
-        ms_s.close()
-        sig_err32 = float(np.max(np.abs(Sg32 - So) / So))
-        cpu = {"value": round(tcpu * scale, 2), "unit": "s", "cores": int(cores), "kind": "oracle",
-               "sample": f"first {m_s} of {A.m} rows ({As.nnz} nnz), same k/s/q/seed; {tcpu:.1f} s measured, "
-                         f"scaled by nnz ratio {scale:.2f}",
-               "gpu_vs_oracle_on_sample": {"sigma_rel_err": sig_err, "sin_theta_V": sin_v,
-                                           "sigma_rel_err_gram_f32": sig_err32}}
-        log(f"oracle on sample: {tcpu:.1f} s -> {tcpu * scale:.1f} s scaled; GPU sigma err {sig_err:.2e} "
-            f"(FP32-MFMA Gram {sig_err32:.2e})")
+    So = None
+    if args.cpu_baseline == "full":
+        cpu, So = cpu_baseline_full(A, k, q, s, (None, S_host, V_host), np)
+    for name, rec in var.items():
+        S2 = rec.pop("S", None)
+        if S2 is not None and So is not None:
+            rec["sigma_rel_err_vs_oracle"] = float(np.max(np.abs(S2 - So) / So))
 
     out = {
-        "metric": "frPCA wall time (s) + SpMM HBM GB/s at k=100; fwd+bwd time vs fwd at stated error",
+        "metric": METRIC,
         "value": round(ms * 1e-3, 6),
         "unit": "s",
         "n_gpus": 1,
@@ -326,18 +484,20 @@ def main():
         "config": {"workload": f"{args.workload} {A.m}x{A.n} CSR, {A.nnz} nnz", "m": A.m, "n": A.n,
                    "nnz": A.nnz, "k": k, "s": s, "passes": q, "seed": SEED,
                    "gram": "fp32-mfma" if args.gram_f32 else "fp64-mfma"},
-        "roofline": roof,
+        "roofline": h["roofline"],
         "cpu_baseline": cpu,
-        "spmm": spmm_report,
-        "gram": gram,
-        "create_ms": round(create_ms, 2),
-        "per_class_ms": {kk: round(v["ms_total_per_step"], 4) for kk, v in per.items()},
-        "ms_per_step_with_class_events": round(ms_timers, 4),
+        "spmm": h["spmm"],
+        "gram": h["gram"],
+        "hbm_copy_measured": copy_peak,
+        "create_ms": round(h["create_ms"], 2),
+        "per_class_ms": {kk: round(v["ms_total_per_step"], 4) for kk, v in h["per"].items()},
+        "ms_per_step_with_class_events": round(h["ms_timers"], 4),
         **extras,
+        "variants": var or None,
+        "zipf_lognormal": secondary,
+        "differentiated": diff,
     }
     print(json.dumps(out), flush=True)
-    matt.close()
-    mat.close()
 
 
 if __name__ == "__main__":

@@ -112,7 +112,8 @@ int frpca_create(frpca_t* out, int64_t m, int64_t n, int64_t nnz, const int64_t*
  * val: device float[nnz] (borrowed as in frpca_create). Asynchronous. */
 int frpca_set_values(frpca_t h, const float* val);
 
-/* frpca_set_stream - enqueue subsequent work of h on `stream`. */
+/* frpca_set_stream - enqueue subsequent work of h on `stream`. When the stream changes, work
+ * on the new stream starts after everything already queued on the old one (an event). */
 int frpca_set_stream(frpca_t h, void* stream);
 
 /*
@@ -131,19 +132,24 @@ int frpca_run(frpca_t h, int k, int p_passes, int s_oversample, uint64_t seed, f
               float* S, float* V);
 
 /*
- * frpca_backward - dL/d(values of A) from dL/dU, dL/dS, dL/dV through the truncated-SVD
- * adjoint, projected onto the sparsity pattern (not part of the paper; the standard SVD
- * reverse-mode rule): with J = U^T dU, K = V^T dV (FP64), F_ij = 1/(s_j^2 - s_i^2) (i != j,
- * 0 where |s_j^2 - s_i^2| <= 1e-12 s_1^2), S+ = diag(1/s_i or 0),
+ * frpca_backward - dL/d(values of A) from dL/dU, dL/dS, dL/dV of the handle's last frpca_run,
+ * through the truncated-SVD adjoint projected onto the sparsity pattern (not part of the
+ * paper; the standard SVD reverse-mode rule): with J = U^T dU, K = V^T dV (FP64),
+ * F_ij = 1/(s_j^2 - s_i^2) (i != j, 0 where |s_j^2 - s_i^2| <= 1e-12 s_1^2),
+ * S+ = diag(1/s_i or 0),
  *   M = (F o (J - J^T)) S + diag(dS) + S (F o (K - K^T)),
  *   dA = U M V^T + (dU - U J) S+ V^T + U S+ (dV - V K)^T,
- * and dval[e] = dA[row(e), col(e)] in CSR order. U (m x k), S (k), V (n x k) are the
- * factors returned by frpca_run for the current values; dU, dS, dV may be NULL (zero).
- * All pointers are device pointers; dval is float[nnz]. Asynchronous.
- * Errors: EINVAL (k < 1, k > min(m, n), k > 128, NULL factor or dval), ENOMEM, EHIP.
+ * and dval[e] = dA[row(e), col(e)] in CSR order (with opts.center, the gradient with
+ * respect to A's stored values through the centring).
+ * The factors U, S, V are those the last frpca_run computed: the library keeps what it needs
+ * to rebuild them (the run's long-side panel, short-side basis, final coefficients with the
+ * sign convention, and S), so the caller's output buffers may be reused or freed.
+ * dU (device float[m*k], row-major), dS (float[k]), dV (float[n*k]) may each be NULL (zero);
+ * k is the last run's. dval: device float[nnz]. Asynchronous.
+ * Errors: ESTATE (no frpca_run since frpca_create, or frpca_set_values since the last run,
+ * or the last run failed), EINVAL (NULL dval with nnz > 0), ENOMEM, EHIP.
  */
-int frpca_backward(frpca_t h, int k, const float* U, const float* S, const float* V,
-                   const float* dU, const float* dS, const float* dV, float* dval);
+int frpca_backward(frpca_t h, const float* dU, const float* dS, const float* dV, float* dval);
 
 /* frpca_get_info - sizes, orientation, last run's parameters and timers (host struct).
  * Synchronises the handle's stream when timing is enabled. */
@@ -213,6 +219,13 @@ int frpca_tsmm(frpca_t h, int64_t rows, int kdim, int c, const float* X, int ldx
  * order; P1, P2: device float[m*w] (ld w), Q1, Q2: device float[n*w]; P2/Q2 may be NULL. */
 int frpca_sddmm(frpca_t h, int w, const float* P1, const float* Q1, const float* P2,
                 const float* Q2, float* dval);
+
+/* The adjoint of frpca_backward at caller-given factors: U (device float[m*k]), S (float[k],
+ * descending, as frpca_run returns them), V (float[n*k]), 1 <= k <= min(m, n, 128); dU, dS, dV
+ * may be NULL. A pure function of its arguments (it neither needs nor uses the last run).
+ * Asynchronous. Errors: EINVAL, ENOMEM, EHIP. */
+int frpca_adjoint(frpca_t h, int k, const float* U, const float* S, const float* V, const float* dU,
+                  const float* dS, const float* dV, float* dval);
 
 /* Copy of the column-major mirror built by frpca_create: col_ptr int64[n+1], row
  * int32[nnz], perm int32[nnz] (CSR position of each column-major nonzero). Device ptrs. */

@@ -48,6 +48,8 @@ class FrPCA:
                          int(center), int(gram_f32))
         self.h = binding.frpca_create(self.m, self.n, self.nnz, self.row_ptr, self.col, self.val, opts,
                                       _stream())
+        self.run_id = 0      # runs so far; frpca_backward refers to the last one
+        self.last_k = 0
 
     @classmethod
     def from_csr(cls, A, device="cuda", **kw):
@@ -61,10 +63,21 @@ class FrPCA:
         binding.frpca_set_stream(self.h, _stream())
 
     def set_values(self, val: torch.Tensor):
-        assert val.dtype == torch.float32 and val.numel() == self.nnz and val.is_cuda
+        assert val.dtype == torch.float32 and val.numel() == self.nnz and val.device == self.device
         self.val = val.contiguous()
         self._sync_stream()
         binding.frpca_set_values(self.h, self.val)
+        self.run_id += 1     # the last run's factors no longer describe the values
+
+    def _panel(self, t, rows, cols, name, dtype=torch.float32):
+        """Check a caller tensor against the shape, dtype and device the C ABI will assume."""
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a torch.Tensor")
+        if tuple(t.shape) != ((rows, cols) if cols is not None else (rows,)):
+            want = (rows, cols) if cols is not None else (rows,)
+            raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {want}")
+        if t.dtype != dtype or t.device != self.device:
+            raise ValueError(f"{name} must be {dtype} on {self.device}, got {t.dtype} on {t.device}")
 
     def run(self, k: int, passes: int, s: int, seed: int, out=None):
         """Rank-k truncated SVD (U m x k, S k descending, V n x k) with q = passes."""
@@ -75,17 +88,44 @@ class FrPCA:
             V = torch.empty((self.n, k), dtype=torch.float32, device=self.device)
         else:
             U, S, V = out
+            for t, rows, cols, name in ((U, self.m, k, "U"), (S, k, None, "S"), (V, self.n, k, "V")):
+                self._panel(t, rows, cols, name)
+                if not t.is_contiguous():
+                    raise ValueError(f"{name} must be contiguous (the library writes it in place)")
         binding.frpca_run(self.h, k, passes, s, seed, U, S, V)
+        self.run_id += 1
+        self.last_k = k
         return U, S, V
 
-    def backward(self, U, S, V, dU=None, dS=None, dV=None):
-        """dL/d(values) (float32[nnz], CSR order) through the truncated-SVD adjoint."""
+    def _grads(self, k, dU, dS, dV):
+        out = []
+        for t, rows, cols, name in ((dU, self.m, k, "dU"), (dS, k, None, "dS"), (dV, self.n, k, "dV")):
+            if t is not None:
+                t = t.to(torch.float32)
+                self._panel(t, rows, cols, name)
+                t = t.contiguous()
+            out.append(t)
+        return out
+
+    def backward(self, dU=None, dS=None, dV=None):
+        """dL/d(values) (float32[nnz], CSR order) through the truncated-SVD adjoint at the
+        factors of this object's last run (frpca_backward; None gradients are zero)."""
+        self._sync_stream()
+        dU, dS, dV = self._grads(self.last_k, dU, dS, dV)
+        dval = torch.empty((self.nnz,), dtype=torch.float32, device=self.device)
+        binding.frpca_backward(self.h, dU, dS, dV, dval)
+        return dval
+
+    def adjoint(self, U, S, V, dU=None, dS=None, dV=None):
+        """The same adjoint at caller-given factors (frpca_adjoint)."""
         self._sync_stream()
         k = S.numel()
-        c = lambda t: None if t is None else t.contiguous().to(torch.float32)  # noqa: E731
+        U, S, V = (t.to(torch.float32) for t in (U, S, V))
+        for t, rows, cols, name in ((U, self.m, k, "U"), (S, k, None, "S"), (V, self.n, k, "V")):
+            self._panel(t, rows, cols, name)
+        dU, dS, dV = self._grads(k, dU, dS, dV)
         dval = torch.empty((self.nnz,), dtype=torch.float32, device=self.device)
-        binding.frpca_backward(self.h, k, U.contiguous(), S.contiguous(), V.contiguous(), c(dU), c(dS), c(dV),
-                               dval)
+        binding.frpca_adjoint(self.h, k, U.contiguous(), S.contiguous(), V.contiguous(), dU, dS, dV, dval)
         return dval
 
     def info(self) -> dict:
@@ -117,16 +157,25 @@ class FrPCA:
 class _FrPCAFunction(torch.autograd.Function):
     @staticmethod
     def forward(ctx, values, mat: FrPCA, k: int, passes: int, s: int, seed: int):
+        # gradients of unused outputs stay None, so the adjoint skips their terms
+        ctx.set_materialize_grads(False)
         mat.set_values(values.detach())
         U, S, V = mat.run(k, passes, s, seed)
         ctx.mat = mat
+        ctx.run_id = mat.run_id
         ctx.save_for_backward(U, S, V)
         return U, S, V
 
     @staticmethod
     def backward(ctx, dU, dS, dV):
         U, S, V = ctx.saved_tensors
-        dval = ctx.mat.backward(U, S, V, dU, dS, dV)
+        mat = ctx.mat
+        if mat.run_id == ctx.run_id:
+            # the handle still holds this forward's factors
+            dval = mat.backward(dU, dS, dV)
+        else:
+            # the handle ran again since: the adjoint at this forward's saved outputs
+            dval = mat.adjoint(U, S, V, dU, dS, dV)
         return dval, None, None, None, None, None
 
 

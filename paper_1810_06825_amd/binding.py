@@ -49,8 +49,9 @@ _SIGNATURES = {
     "frpca_set_values": (c_int, [c_void_p, c_void_p]),
     "frpca_set_stream": (c_int, [c_void_p, c_void_p]),
     "frpca_run": (c_int, [c_void_p, c_int, c_int, c_int, c_uint64, c_void_p, c_void_p, c_void_p]),
-    "frpca_backward": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
-                               c_void_p]),
+    "frpca_backward": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "frpca_adjoint": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                              c_void_p]),
     "frpca_get_info": (c_int, [c_void_p, POINTER(FrpcaInfo)]),
     "frpca_reset_timers": (c_int, [c_void_p]),
     "frpca_last_error": (c_char_p, [c_void_p]),
@@ -124,8 +125,12 @@ def frpca_run(h, k, p_passes, s_oversample, seed, U, S, V):
     _check(load().frpca_run(h, k, p_passes, s_oversample, seed, _ptr(U), _ptr(S), _ptr(V)), h)
 
 
-def frpca_backward(h, k, U, S, V, dU, dS, dV, dval):
-    _check(load().frpca_backward(h, k, _ptr(U), _ptr(S), _ptr(V), _ptr(dU), _ptr(dS), _ptr(dV), _ptr(dval)), h)
+def frpca_backward(h, dU, dS, dV, dval):
+    _check(load().frpca_backward(h, _ptr(dU), _ptr(dS), _ptr(dV), _ptr(dval)), h)
+
+
+def frpca_adjoint(h, k, U, S, V, dU, dS, dV, dval):
+    _check(load().frpca_adjoint(h, k, _ptr(U), _ptr(S), _ptr(V), _ptr(dU), _ptr(dS), _ptr(dV), _ptr(dval)), h)
 
 
 def frpca_get_info(h) -> FrpcaInfo:

@@ -109,15 +109,25 @@ struct frpca_ctx {
   uint16_t *Qb = nullptr, *Yb = nullptr;
   double *gram_part = nullptr, *G = nullptr, *W = nullptr, *d = nullptr;
   double *B1 = nullptr, *B2 = nullptr;
+  float* Skeep = nullptr;  // singular values of the last run (library copy)
   int *order = nullptr, *ndrop = nullptr;
   double* eig_tmp = nullptr;
   float* bpart = nullptr;  // partial rows of the blocked transpose product
   void *lu_tmp = nullptr, *sign_tmp = nullptr;
 
+  // Factors of the last frpca_run, kept for frpca_backward: the long-side panel Z, the
+  // short-side basis Q, the final coefficients B1 (long) and B2 (short) with the sign
+  // convention folded in, and S. U and V are rebuilt from them (U = Z B1, V = Q B2 for
+  // Alg. 6; swapped for Alg. 5). saved_k = 0: no valid factors.
+  int saved_k = 0, saved_l = 0, saved_ld = 0;  // k, l and panel leading dimension of that run
+
   // backward workspace
   void* bws = nullptr;
   size_t bws_bytes = 0;
   int bws_k = 0;
+
+  // ordering of work when the caller switches streams
+  hipEvent_t handoff = nullptr;
 
   frpca_info info{};
   struct Pending {
@@ -137,6 +147,7 @@ struct frpca_ctx {
       (void)hipEventDestroy(p.b);
     }
     for (auto e : pool) (void)hipEventDestroy(e);
+    if (handoff) (void)hipEventDestroy(handoff);
     for (void* p : owned) (void)hipFree(p);
     if (ws) (void)hipFree(ws);
     if (bws) (void)hipFree(bws);
@@ -237,6 +248,7 @@ struct frpca_ctx {
       FRPCA_HIP(hipFree(ws));
       ws = nullptr;
       ws_bytes = 0;
+      saved_k = 0;
     }
     const int64_t Ns = short_rows(), Nl = long_rows();
     auto plan = [&](Arena& a) {
@@ -251,6 +263,7 @@ struct frpca_ctx {
       W = a.take<double>(kMaxL * kMaxL);
       B1 = a.take<double>(kMaxL * kMaxL);
       B2 = a.take<double>(kMaxL * kMaxL);
+      Skeep = a.take<float>(kMaxL);
       d = a.take<double>(kMaxL);
       order = a.take<int>(kMaxL);
       eig_tmp = a.take<double>(eig_scratch_bytes() / sizeof(double));
@@ -457,6 +470,7 @@ int frpca_set_values(frpca_t h, const float* val) {
     FRPCA_CHECK(val != nullptr || h->nnz == 0, FRPCA_EINVAL, "NULL values");
     h->val = val;
     h->csr.val = val;
+    h->saved_k = 0;  // the last run's factors belong to the old values
     launch_gather_values(h->perm, val, h->nnz, h->val_csc, h->stream);
     if (h->has_bcsc) launch_gather_values(h->bperm, val, h->nnz, h->bval, h->stream);
     if (h->opts.center) launch_colmean(h->cp32, h->val_csc, h->n, h->m, h->mu, h->stream);
@@ -466,8 +480,15 @@ int frpca_set_values(frpca_t h, const float* val) {
 
 int frpca_set_stream(frpca_t h, void* stream) {
   if (!h) return fail(nullptr, Error{FRPCA_EINVAL, "NULL handle"});
-  h->stream = static_cast<hipStream_t>(stream);
-  return FRPCA_OK;
+  return guarded(h, [&] {
+    hipStream_t ns = static_cast<hipStream_t>(stream);
+    if (ns == h->stream) return;
+    // work queued on the old stream uses the handle's buffers: the new stream starts after it
+    if (!h->handoff) FRPCA_HIP(hipEventCreateWithFlags(&h->handoff, hipEventDisableTiming));
+    FRPCA_HIP(hipEventRecord(h->handoff, h->stream));
+    FRPCA_HIP(hipStreamWaitEvent(ns, h->handoff, 0));
+    h->stream = ns;
+  });
 }
 
 int frpca_run(frpca_t h, int k, int p_passes, int s_oversample, uint64_t seed, float* U, float* S, float* V) {
@@ -482,6 +503,7 @@ int frpca_run(frpca_t h, int k, int p_passes, int s_oversample, uint64_t seed, f
     FRPCA_CHECK(U && S && V, FRPCA_EINVAL, "NULL output");
     const int LP = panel_ld(l);
     const int bf = h->opts.panel_bf16 ? 1 : 0;
+    h->saved_k = 0;
     h->ensure_workspace(LP, bf);
     hipStream_t st = h->stream;
     const bool a6 = m >= n;
@@ -585,7 +607,7 @@ int frpca_run(frpca_t h, int k, int p_passes, int s_oversample, uint64_t seed, f
     // final pass and Rayleigh-Ritz: eigSVD of the long-side panel Z
     spmm(Fp, fwd_cls, h->Q, false, h->Z, nullptr, forward_corr(h->Q, false));
     gram_eig(h->Z, Nl);
-    launch_final_coeffs(h->d, h->W, l, k, LP, h->rank_tol, h->B1, h->B2, S, h->ndrop, st);
+    launch_final_coeffs(h->d, h->W, l, k, LP, h->rank_tol, h->B1, h->B2, S, h->Skeep, h->ndrop, st);
     // B1 multiplies the long-side panel Z, B2 the short-side basis Q
     float* out_long = a6 ? U : V;
     float* out_short = a6 ? V : U;
@@ -601,14 +623,14 @@ int frpca_run(frpca_t h, int k, int p_passes, int s_oversample, uint64_t seed, f
       tsmm_short();
       if (!h->opts.no_sign_fix) {
         frpca_ctx::Scope t(h, FRPCA_T_SIGN);
-        launch_sign_fix(V, n, k, h->B1, LP, l, h->sign_tmp, st);
+        launch_sign_fix(V, n, k, h->B1, h->B2, LP, l, h->sign_tmp, st);
       }
       tsmm_long();
     } else {
       tsmm_long();
       if (!h->opts.no_sign_fix) {
         frpca_ctx::Scope t(h, FRPCA_T_SIGN);
-        launch_sign_fix(V, n, k, h->B2, LP, l, h->sign_tmp, st);
+        launch_sign_fix(V, n, k, h->B2, h->B1, LP, l, h->sign_tmp, st);
       }
       tsmm_short();
     }
@@ -616,80 +638,138 @@ int frpca_run(frpca_t h, int k, int p_passes, int s_oversample, uint64_t seed, f
     h->info.k = k;
     h->info.s = s_oversample;
     h->info.passes = p_passes;
+    h->saved_k = k;
+    h->saved_l = l;
+    h->saved_ld = LP;
   });
 }
 
-int frpca_backward(frpca_t h, int k, const float* U, const float* S, const float* V, const float* dU,
-                   const float* dS, const float* dV, float* dval) {
+// Adjoint at the factors (U m x k, S, V n x k), projected on the pattern. With `saved` the
+// factors are the last run's, rebuilt from the library's panels; otherwise they are the
+// caller's (leading dimension k). Every panel of the adjoint has leading dimension k rounded
+// up to 4 with zero pad columns, so the products run on 16-byte rows at any k.
+static void adjoint_impl(frpca_ctx* h, int k, const float* Uc, const float* Sc, const float* Vc, const float* dU,
+                  const float* dS, const float* dV, float* dval, bool saved) {
+  const int64_t m = h->m, n = h->n;
+  const int kp = (k + 3) / 4 * 4;
+  hipStream_t st = h->stream;
+  auto plan = [&](Arena& a, double*& part, double*& J, double*& K, double*& CU, double*& CV, double*& SP,
+                  float*& Ui, float*& Vi, float*& L1, float*& R2, float*& dUp, float*& dVp, double*& wpart,
+                  float*& ell, float*& corr) {
+    part = a.take<double>(gram_partial_bytes(kp) / sizeof(double));
+    J = a.take<double>((size_t)kp * kp);
+    K = a.take<double>((size_t)kp * kp);
+    CU = a.take<double>((size_t)kp * kp);
+    CV = a.take<double>((size_t)kp * kp);
+    SP = a.take<double>((size_t)kp * kp);
+    Ui = a.take<float>((size_t)m * kp);
+    Vi = a.take<float>((size_t)n * kp);
+    L1 = a.take<float>((size_t)m * kp);
+    R2 = a.take<float>((size_t)n * kp);
+    dUp = a.take<float>((size_t)m * kp);
+    dVp = a.take<float>((size_t)n * kp);
+    wpart = h->opts.center ? a.take<double>(wsum_temp_bytes(m) / sizeof(double)) : nullptr;
+    ell = h->opts.center ? a.take<float>(2 * kMaxL) : nullptr;
+    corr = h->opts.center ? a.take<float>(std::max<int64_t>(n, 1)) : nullptr;
+  };
+  double *part, *J, *K, *CU, *CV, *SP, *wpart;
+  float *Ui, *Vi, *L1, *R2, *dUp, *dVp, *ell, *corr;
+  if (!h->bws || h->bws_k < kp) {
+    if (h->bws) {
+      FRPCA_HIP(hipStreamSynchronize(st));
+      FRPCA_HIP(hipFree(h->bws));
+      h->bws = nullptr;
+      h->bws_bytes = 0;
+      h->bws_k = 0;
+    }
+    Arena probe;
+    plan(probe, part, J, K, CU, CV, SP, Ui, Vi, L1, R2, dUp, dVp, wpart, ell, corr);
+    if (h->opts.max_workspace && probe.used + h->setup_bytes + h->ws_bytes > h->opts.max_workspace)
+      throw Error{FRPCA_ENOMEM, "backward workspace exceeds opts.max_workspace"};
+    if (hipMalloc(&h->bws, probe.used) != hipSuccess) {
+      (void)hipGetLastError();
+      h->bws = nullptr;
+      throw Error{FRPCA_ENOMEM, "backward workspace allocation failed"};
+    }
+    h->bws_bytes = probe.used;
+    h->bws_k = kp;
+  }
+  Arena a;
+  a.base = static_cast<char*>(h->bws);
+  plan(a, part, J, K, CU, CV, SP, Ui, Vi, L1, R2, dUp, dVp, wpart, ell, corr);
+
+  auto aligned = [](const float* p) { return (reinterpret_cast<uintptr_t>(p) % 16) == 0; };
+  // a caller panel (rows x k) as a kp-wide panel: used in place when it already is one
+  auto widen = [&](const float* src, int64_t rows, float* buf) -> const float* {
+    if (src == nullptr) return nullptr;
+    if (kp == k && aligned(src)) return src;
+    launch_pad_copy(src, k, rows, k, buf, kp, st);
+    return buf;
+  };
+  const float* U;
+  const float* V;
+  const float* S;
+  {
+    frpca_ctx::Scope t(h, FRPCA_T_BWD);
+    if (saved) {
+      // U = Z B1, V = Q B2 (Alg. 6) or U = Q B2, V = Z B1 (Alg. 5), as the run formed them
+      const int LP = h->saved_ld, l = h->saved_l;
+      const bool a6 = m >= n;
+      launch_tsmm(h->Z, false, LP, h->long_rows(), l, h->B1, LP, k, kp, a6 ? Ui : Vi, kp, nullptr, 0, st);
+      launch_tsmm(h->Q, false, LP, h->short_rows(), l, h->B2, LP, k, kp, a6 ? Vi : Ui, kp, nullptr, 0, st);
+      U = Ui;
+      V = Vi;
+      S = h->Skeep;
+    } else {
+      U = widen(Uc, m, Ui);
+      V = widen(Vc, n, Vi);
+      S = Sc;
+    }
+    const float* dUk = widen(dU, m, dUp);
+    const float* dVk = widen(dV, n, dVp);
+    if (dU) launch_gram(U, false, kp, dUk, kp, m, k, part, J, k, st);
+    if (dV) launch_gram(V, false, kp, dVk, kp, n, k, part, K, k, st);
+    launch_adjoint_small(J, K, S, dS, k, dU != nullptr, dV != nullptr, CU, CV, SP, st);
+    // L1 = U CU + dU SP and R2 = V CV + dV SP, SP diagonal: one pass each, the dU (dV) term
+    // added in the product's epilogue; pad columns come out 0
+    launch_tsmm(U, false, kp, m, k, CU, k, k, kp, L1, kp, nullptr, 0, st, dUk, kp, dU ? SP : nullptr, k);
+    if (dV) launch_tsmm(V, false, kp, n, k, CV, k, k, kp, R2, kp, nullptr, 0, st, dVk, kp, SP, k);
+    // centred matrix: dA = (I - 1 1^T / m) G for the dense adjoint G = L1 V^T + U R2^T, so
+    // each row of L1 and of U loses its column mean and dval[e] drops corr[c] = l1.V[c] + lU.R2[c]
+    if (h->opts.center) {
+      launch_wsum(L1, false, kp, m, kp, nullptr, 1.0 / (double)m, wpart, ell, st);
+      if (dV) launch_wsum(U, false, kp, m, kp, nullptr, 1.0 / (double)m, wpart, ell + kMaxL, st);
+      launch_center_corr(ell, V, ell + kMaxL, dV ? R2 : nullptr, n, k, kp, corr, st);
+    }
+  }
+  {
+    frpca_ctx::Scope t(h, FRPCA_T_SDDMM);
+    launch_sddmm(h->rp32, h->col, m, kp, L1, V, dV ? U : nullptr, dV ? R2 : nullptr, dval, st,
+                 h->opts.center ? corr : nullptr);
+  }
+  check_launch();
+}
+
+int frpca_backward(frpca_t h, const float* dU, const float* dS, const float* dV, float* dval) {
+  if (!h) return fail(nullptr, Error{FRPCA_EINVAL, "NULL handle"});
+  return guarded(h, [&] {
+    FRPCA_CHECK(dval != nullptr || h->nnz == 0, FRPCA_EINVAL, "NULL dval");
+    FRPCA_CHECK(h->saved_k > 0, FRPCA_ESTATE,
+                "frpca_backward needs the factors of a frpca_run on this handle (none since create or "
+                "since the last frpca_set_values)");
+    adjoint_impl(h, h->saved_k, nullptr, nullptr, nullptr, dU, dS, dV, dval, true);
+  });
+}
+
+int frpca_adjoint(frpca_t h, int k, const float* U, const float* S, const float* V, const float* dU,
+                  const float* dS, const float* dV, float* dval) {
   if (!h) return fail(nullptr, Error{FRPCA_EINVAL, "NULL handle"});
   return guarded(h, [&] {
     const int64_t m = h->m, n = h->n;
     FRPCA_CHECK(k >= 1 && k <= std::min<int64_t>(std::min(m, n), kMaxL), FRPCA_EINVAL,
                 "need 1 <= k <= min(m, n, 128)");
-    FRPCA_CHECK(U && S && V && dval, FRPCA_EINVAL, "NULL factor or output");
-    hipStream_t st = h->stream;
-    if (!h->bws || h->bws_k < k) {
-      if (h->bws) {
-        FRPCA_HIP(hipStreamSynchronize(st));
-        FRPCA_HIP(hipFree(h->bws));
-        h->bws = nullptr;
-      }
-      Arena probe;
-      probe.take<double>(gram_partial_bytes(k) / sizeof(double));
-      probe.take<double>(5 * (size_t)k * k);
-      probe.take<float>((size_t)m * k);
-      probe.take<float>((size_t)n * k);
-      if (h->opts.center) {
-        probe.take<double>(wsum_temp_bytes(m) / sizeof(double));
-        probe.take<float>(2 * kMaxL);
-        probe.take<float>(std::max<int64_t>(n, 1));
-      }
-      if (h->opts.max_workspace && probe.used + h->setup_bytes + h->ws_bytes > h->opts.max_workspace)
-        throw Error{FRPCA_ENOMEM, "backward workspace exceeds opts.max_workspace"};
-      if (hipMalloc(&h->bws, probe.used) != hipSuccess) {
-        (void)hipGetLastError();
-        h->bws = nullptr;
-        throw Error{FRPCA_ENOMEM, "backward workspace allocation failed"};
-      }
-      h->bws_bytes = probe.used;
-      h->bws_k = k;
-    }
-    Arena a;
-    a.base = static_cast<char*>(h->bws);
-    double* part = a.take<double>(gram_partial_bytes(k) / sizeof(double));
-    double* J = a.take<double>((size_t)k * k);
-    double* K = a.take<double>((size_t)k * k);
-    double* CU = a.take<double>((size_t)k * k);
-    double* CV = a.take<double>((size_t)k * k);
-    double* SP = a.take<double>((size_t)k * k);
-    float* L1 = a.take<float>((size_t)m * k);
-    float* R2 = a.take<float>((size_t)n * k);
-    // centred matrix: dA = (I - 1 1^T / m) G for the dense adjoint G = L1 V^T + U R2^T, so each
-    // row of L1 and of U loses its column mean and dval[e] drops corr[c] = l1.V[c] + lU.R2[c]
-    const bool cen = h->opts.center != 0;
-    double* wpart = cen ? a.take<double>(wsum_temp_bytes(m) / sizeof(double)) : nullptr;
-    float* ell = cen ? a.take<float>(2 * kMaxL) : nullptr;
-    float* corr = cen ? a.take<float>(std::max<int64_t>(n, 1)) : nullptr;
-    {
-      frpca_ctx::Scope t(h, FRPCA_T_BWD);
-      if (dU) launch_gram(U, false, k, dU, k, m, k, part, J, k, st);
-      if (dV) launch_gram(V, false, k, dV, k, n, k, part, K, k, st);
-      launch_adjoint_small(J, K, S, dS, k, dU != nullptr, dV != nullptr, CU, CV, SP, st);
-      // L1 = U CU + dU SP and R2 = V CV + dV SP, SP diagonal: one pass each, the dU (dV)
-      // term added in the product's epilogue
-      launch_tsmm(U, false, k, m, k, CU, k, k, k, L1, k, nullptr, 0, st, dU, k, dU ? SP : nullptr, k);
-      if (dV) launch_tsmm(V, false, k, n, k, CV, k, k, k, R2, k, nullptr, 0, st, dV, k, SP, k);
-      if (cen) {
-        launch_wsum(L1, false, k, m, k, nullptr, 1.0 / (double)m, wpart, ell, st);
-        if (dV) launch_wsum(U, false, k, m, k, nullptr, 1.0 / (double)m, wpart, ell + kMaxL, st);
-        launch_center_corr(ell, V, ell + kMaxL, dV ? R2 : nullptr, n, k, corr, st);
-      }
-    }
-    {
-      frpca_ctx::Scope t(h, FRPCA_T_SDDMM);
-      launch_sddmm(h->rp32, h->col, m, k, L1, V, dV ? U : nullptr, dV ? R2 : nullptr, dval, st, corr);
-    }
-    check_launch();
+    FRPCA_CHECK(U && S && V && (dval || h->nnz == 0), FRPCA_EINVAL, "NULL factor or output");
+    adjoint_impl(h, k, U, S, V, dU, dS, dV, dval, false);
   });
 }
 

@@ -73,20 +73,37 @@ __global__ __launch_bounds__(128) void wsum_final_kernel(const double* part, int
   v[c] = (float)(scale * s);
 }
 
-// corr[c] = a . V[c, :] + b . R[c, :] (k-vectors a, b; R may be null)
+// corr[c] = a . V[c, :] + b . R[c, :] (k-vectors a, b; R may be null; V and R with leading
+// dimension ld)
 __global__ __launch_bounds__(256) void center_corr_kernel(const float* a, const float* V, const float* b,
-                                                          const float* R, int64_t n, int k, float* corr) {
+                                                          const float* R, int64_t n, int k, int ld, float* corr) {
   const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (c >= n) return;
   double s = 0.0;
   for (int i = 0; i < k; ++i) {
-    s += (double)a[i] * (double)V[(size_t)c * k + i];
-    if (R) s += (double)b[i] * (double)R[(size_t)c * k + i];
+    s += (double)a[i] * (double)V[(size_t)c * ld + i];
+    if (R) s += (double)b[i] * (double)R[(size_t)c * ld + i];
   }
   corr[c] = (float)s;
 }
 
+// dst[r, c] = src[r, c] for c < cols, 0 for cols <= c < ldd (one thread per destination entry)
+__global__ __launch_bounds__(256) void pad_copy_kernel(const float* src, int lds, int64_t rows, int cols, float* dst,
+                                                       int ldd) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= rows * ldd) return;
+  const int64_t r = idx / ldd;
+  const int c = (int)(idx - r * ldd);
+  dst[idx] = c < cols ? src[(size_t)r * lds + c] : 0.f;
+}
+
 }  // namespace
+
+void launch_pad_copy(const float* src, int lds, int64_t rows, int cols, float* dst, int ldd, hipStream_t st) {
+  const int64_t total = rows * ldd;
+  if (total <= 0) return;
+  pad_copy_kernel<<<(unsigned)((total + 255) / 256), 256, 0, st>>>(src, lds, rows, cols, dst, ldd);
+}
 
 void launch_colmean(const int32_t* cp, const float* val, int64_t n, int64_t m, float* mu, hipStream_t st) {
   if (n <= 0) return;
@@ -108,10 +125,10 @@ void launch_wsum(const void* P, bool bf16, int ldp, int64_t rows, int lp, const 
   wsum_final_kernel<<<1, 128, 0, st>>>(part, nblk, lp, scale, v);
 }
 
-void launch_center_corr(const float* a, const float* V, const float* b, const float* R, int64_t n, int k, float* corr,
-                        hipStream_t st) {
+void launch_center_corr(const float* a, const float* V, const float* b, const float* R, int64_t n, int k, int ld,
+                        float* corr, hipStream_t st) {
   if (n <= 0) return;
-  center_corr_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(a, V, b, R, n, k, corr);
+  center_corr_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(a, V, b, R, n, k, ld, corr);
 }
 
 }  // namespace frpca

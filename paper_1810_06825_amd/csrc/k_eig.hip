@@ -30,7 +30,7 @@ __global__ __launch_bounds__(256) void eigsvd_coeffs_kernel(const double* d, con
 // Final selection ind = l-1, ..., l-k (k+s:-1:s+1 in the paper's 1-based notation).
 __global__ __launch_bounds__(256) void final_coeffs_kernel(const double* d, const double* W, int l, int k, int ldb,
                                                            double rank_tol, double* Blong, double* Bshort,
-                                                           float* S, int* ndropped) {
+                                                           float* S, float* S_keep, int* ndropped) {
   const double smax = sqrt(fmax(d[l - 1], 0.0));
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx < l * ldb) {
@@ -56,6 +56,7 @@ __global__ __launch_bounds__(256) void final_coeffs_kernel(const double* d, cons
       const double s = sqrt(fmax(d[l - 1 - i], 0.0));
       const bool keep = s > rank_tol * smax && s > 0.0;
       S[i] = keep ? (float)s : 0.0f;
+      if (S_keep) S_keep[i] = S[i];
       drop = !keep;
     }
     const uint64_t m = __ballot(drop);
@@ -89,9 +90,11 @@ __global__ __launch_bounds__(256) void sign_partial_kernel(const float* V, int64
 }
 
 // One block per column i: reduce the per-block candidates (|v|, row) in block order (ties:
-// lowest row), then fold the sign into column i of Blong.
+// lowest row), then fold the sign into column i of both coefficient matrices (B_other may be
+// null), so either factor rebuilt from them carries the convention.
 __global__ __launch_bounds__(256) void sign_final_kernel(const float* V, int k, int nblk, const float* pv,
-                                                         const int* pr, float* sgn, double* Blong, int ldb, int l) {
+                                                         const int* pr, float* sgn, double* Blong, double* B_other,
+                                                         int ldb, int l) {
   __shared__ float sv[256];
   __shared__ int sr[256];
   const int i = blockIdx.x, t = threadIdx.x;
@@ -122,7 +125,10 @@ __global__ __launch_bounds__(256) void sign_final_kernel(const float* V, int k, 
   const float s = (V[(size_t)sr[0] * k + i] < 0.0f) ? -1.0f : 1.0f;
   if (t == 0) sgn[i] = s;
   if (s < 0.0f)
-    for (int a = t; a < l; a += 256) Blong[(size_t)a * ldb + i] = -Blong[(size_t)a * ldb + i];
+    for (int a = t; a < l; a += 256) {
+      Blong[(size_t)a * ldb + i] = -Blong[(size_t)a * ldb + i];
+      if (B_other) B_other[(size_t)a * ldb + i] = -B_other[(size_t)a * ldb + i];
+    }
 }
 
 __global__ __launch_bounds__(256) void sign_apply_kernel(float* V, int64_t rows, int k, const float* sgn) {
@@ -141,8 +147,9 @@ void launch_eigsvd_coeffs(const double* d, const double* W, int l, int ldb, doub
 }
 
 void launch_final_coeffs(const double* d, const double* W, int l, int k, int ldb, double rank_tol, double* Blong,
-                         double* Bshort, float* S, int* ndropped, hipStream_t st) {
-  final_coeffs_kernel<<<(l * ldb + 255) / 256, 256, 0, st>>>(d, W, l, k, ldb, rank_tol, Blong, Bshort, S, ndropped);
+                         double* Bshort, float* S, float* S_keep, int* ndropped, hipStream_t st) {
+  final_coeffs_kernel<<<(l * ldb + 255) / 256, 256, 0, st>>>(d, W, l, k, ldb, rank_tol, Blong, Bshort, S, S_keep,
+                                                            ndropped);
 }
 
 size_t sign_partial_bytes(int64_t rows, int k) {
@@ -150,14 +157,14 @@ size_t sign_partial_bytes(int64_t rows, int k) {
   return (size_t)nblk * k * (sizeof(float) + sizeof(int)) + (size_t)k * sizeof(float) + 256;
 }
 
-void launch_sign_fix(float* V, int64_t rows, int k, double* Blong, int ldb, int brows, void* partial,
+void launch_sign_fix(float* V, int64_t rows, int k, double* Blong, double* B_other, int ldb, int brows, void* partial,
                      hipStream_t st) {
   const int64_t nblk = (rows + kSignRows - 1) / kSignRows;
   float* pv = static_cast<float*>(partial);
   int* pr = reinterpret_cast<int*>(pv + nblk * k);
   float* sgn = reinterpret_cast<float*>(pr + nblk * k);
   sign_partial_kernel<<<(unsigned)nblk, 256, 0, st>>>(V, rows, k, pv, pr);
-  sign_final_kernel<<<k, 256, 0, st>>>(V, k, (int)nblk, pv, pr, sgn, Blong, ldb, brows);
+  sign_final_kernel<<<k, 256, 0, st>>>(V, k, (int)nblk, pv, pr, sgn, Blong, B_other, ldb, brows);
   sign_apply_kernel<<<(unsigned)((rows * k + 255) / 256), 256, 0, st>>>(V, rows, k, sgn);
 }
 

@@ -68,8 +68,10 @@ void launch_colmean(const int32_t* cp, const float* val, int64_t n, int64_t m, f
 size_t wsum_temp_bytes(int64_t rows);
 void launch_wsum(const void* P, bool bf16, int ldp, int64_t rows, int lp, const float* w, double scale, double* part,
                  float* v, hipStream_t st);
-void launch_center_corr(const float* a, const float* V, const float* b, const float* R, int64_t n, int k, float* corr,
-                        hipStream_t st);
+void launch_center_corr(const float* a, const float* V, const float* b, const float* R, int64_t n, int k, int ld,
+                        float* corr, hipStream_t st);
+// dst (rows x ldd) = src (rows x cols, leading dimension lds) with zero columns cols..ldd-1
+void launch_pad_copy(const float* src, int lds, int64_t rows, int cols, float* dst, int ldd, hipStream_t st);
 
 // ---------------------------------------------------------------- merge-path products
 struct MergePlan {
@@ -129,14 +131,16 @@ void launch_eig(const double* G, int ldg, int l, double* d, double* W, double* s
 void launch_eigsvd_coeffs(const double* d, const double* W, int l, int ldb, double tol,
                           double* B, double* sigma, hipStream_t st);
 // Final Rayleigh-Ritz selection ind = l-1 .. l-k: S[i] = sigma_{l-1-i},
-// Blong[a][i] = W[a][l-1-i]/S[i], Bshort[a][i] = W[a][l-1-i]; dropped -> 0.
+// Blong[a][i] = W[a][l-1-i]/S[i], Bshort[a][i] = W[a][l-1-i]; dropped -> 0. S_keep (optional)
+// receives a copy of S.
 void launch_final_coeffs(const double* d, const double* W, int l, int k, int ldb,
-                         double rank_tol, double* Blong, double* Bshort, float* S,
+                         double rank_tol, double* Blong, double* Bshort, float* S, float* S_keep,
                          int* ndropped, hipStream_t st);
 // Sign convention on V (rows x k, ld k): sign_i = sign of V's largest-|.| entry of column i.
 size_t sign_partial_bytes(int64_t rows, int k);
-// Blong (brows x ldb) gets the same column signs, so U = Z Blong inherits them.
-void launch_sign_fix(float* V, int64_t rows, int k, double* Blong, int ldb, int brows, void* partial,
+// Blong and B_other (brows x ldb; B_other may be null) get the same column signs, so factors
+// formed from them (U = Z Blong before or after, V = Q B_other again later) inherit them.
+void launch_sign_fix(float* V, int64_t rows, int k, double* Blong, double* B_other, int ldb, int brows, void* partial,
                      hipStream_t st);
 
 // LU basis (tournament pivoting) -> coefficient matrix B (l x l, FP64, ldb) with Q = X B.

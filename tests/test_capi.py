@@ -67,7 +67,8 @@ def test_invalid_arguments_rejected_without_gpu(lib):
     o.rank_tol = 2.0
     assert lib.frpca_create(ctypes.byref(h), 4, 5, 0, 1, None, None, ctypes.byref(o), None) == binding.FRPCA_EINVAL
     for call in (lambda: lib.frpca_run(None, 5, 3, 2, 1, None, None, None),
-                 lambda: lib.frpca_backward(None, 5, None, None, None, None, None, None, None),
+                 lambda: lib.frpca_backward(None, None, None, None, None),
+                 lambda: lib.frpca_adjoint(None, 5, None, None, None, None, None, None, None),
                  lambda: lib.frpca_set_values(None, None),
                  lambda: lib.frpca_spmm(None, 0, 4, None, 0, 4, None, 0, 4)):
         assert call() == binding.FRPCA_EINVAL

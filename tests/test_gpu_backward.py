@@ -10,7 +10,7 @@ from synth import zipf_normal
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-from paper_1810_06825_amd import FrPCA, frpca_autograd  # noqa: E402
+from paper_1810_06825_amd import FrPCA, FrpcaError, binding, frpca_autograd  # noqa: E402
 
 DEV = "cuda:0"
 
@@ -34,12 +34,65 @@ def test_backward_matches_fp64_formula_at_gpu_factors(k, t):
     dV = torch.from_numpy(rng.standard_normal((A.n, k)).astype(np.float32)).to(DEV)
     dS = torch.from_numpy(rng.standard_normal(k).astype(np.float32)).to(DEV)
     for args in ((None, dS, None), (dU, None, None), (None, None, dV), (dU, dS, dV)):
-        dval = mat.backward(U, S, V, *args)
+        # frpca_backward rebuilds the run's factors; frpca_adjoint takes them from the caller
+        dval = mat.backward(*args)
+        dval_x = mat.adjoint(U, S, V, *args)
         ref = oracle.svd_adjoint_values(np64(U), np64(S), np64(V),
                                         *(None if a is None else np64(a) for a in args), _rows(A), A.col)
         err = np.abs(np64(dval) - ref).max() / np.abs(ref).max()
-        say("  terms", [a is not None for a in args], "rel err", err)
-        assert err < 1e-4
+        err_x = np.abs(np64(dval_x) - ref).max() / np.abs(ref).max()
+        say("  terms", [a is not None for a in args], "rel err", err, "explicit factors", err_x)
+        assert err < 1e-4 and err_x < 1e-4
+        # the rebuilt factors are the ones the run returned: both entry points agree to rounding
+        assert np.abs(np64(dval) - np64(dval_x)).max() <= 1e-6 * np.abs(ref).max()
+    mat.close()
+
+
+def test_backward_needs_a_run():
+    """frpca_backward refers to the handle's last run: none yet, or values changed since,
+    is a state error; after a run it succeeds; frpca_adjoint works without a run."""
+    A = zipf_normal(m=5_000, n=1_000, t=20)
+    mat = FrPCA.from_csr(A, device=DEV)
+    k = 10
+    dS = torch.ones(k, device=DEV)
+    with pytest.raises(FrpcaError) as ei:
+        binding.frpca_backward(mat.h, None, dS, None, torch.empty(A.nnz, device=DEV))
+    assert ei.value.code == binding.FRPCA_ESTATE
+    U, S, V = mat.run(k, 3, 5, 1)
+    g = mat.backward(None, dS, None)
+    mat.set_values(mat.val.clone())
+    with pytest.raises(FrpcaError) as ei:
+        binding.frpca_backward(mat.h, None, dS, None, torch.empty(A.nnz, device=DEV))
+    assert ei.value.code == binding.FRPCA_ESTATE
+    # the explicit-factor adjoint is a pure function of its arguments
+    g2 = mat.adjoint(U, S, V, None, dS, None)
+    assert torch.allclose(g, g2, rtol=0, atol=1e-6 * float(g.abs().max()))
+    # a later run with another k: backward follows the new run
+    U3, S3, V3 = mat.run(12, 4, 4, 2)
+    g3 = mat.backward(None, torch.ones(12, device=DEV), None)
+    ref3 = oracle.svd_adjoint_values(np64(U3), np64(S3), np64(V3), None, np.ones(12), None, _rows(A), A.col)
+    assert np.abs(np64(g3) - ref3).max() <= 1e-4 * np.abs(ref3).max()
+    mat.close()
+
+
+@pytest.mark.parametrize("k", [50, 51])
+def test_backward_unaligned_k(k):
+    """k not a multiple of 4 (the differentiated workload's k = 50): the panels are padded to
+    16-byte rows; the result matches the FP64 formula with every term present."""
+    A = zipf_normal(m=30_000, n=6_000, t=30)
+    mat = FrPCA.from_csr(A, device=DEV)
+    U, S, V = mat.run(k, 4, 10, 5)
+    rng = np.random.default_rng(9)
+    dU = torch.from_numpy(rng.standard_normal((A.m, k)).astype(np.float32)).to(DEV)
+    dV = torch.from_numpy(rng.standard_normal((A.n, k)).astype(np.float32)).to(DEV)
+    dS = torch.from_numpy(rng.standard_normal(k).astype(np.float32)).to(DEV)
+    for args in ((dU, dS, None), (dU, dS, dV)):
+        ref = oracle.svd_adjoint_values(np64(U), np64(S), np64(V),
+                                        *(None if a is None else np64(a) for a in args), _rows(A), A.col)
+        for dval in (mat.backward(*args), mat.adjoint(U, S, V, *args)):
+            err = np.abs(np64(dval) - ref).max() / np.abs(ref).max()
+            say("  k", k, "terms", [a is not None for a in args], "rel err", err)
+            assert err < 1e-4
     mat.close()
 
 

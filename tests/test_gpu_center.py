@@ -84,13 +84,14 @@ def test_centred_backward_matches_fp64_formula(k):
     say("centred backward", A.m, A.n, A.nnz, k)
     rows = np.repeat(np.arange(A.m), np.diff(A.row_ptr))
     # without dV the sampled product has one term (its own kernel variant)
-    g1 = np64(mat.backward(U, S, V, dU, dS, None))
+    g1 = np64(mat.backward(dU, dS, None))
     ref1 = oracle.svd_adjoint_values(np64(U), np64(S), np64(V), np64(dU), np64(dS), None, rows, A.col,
                                      center=True)
     err1 = np.abs(g1 - ref1).max() / np.abs(ref1).max()
     say("  rel err without dV", err1)
     assert err1 < 1e-4
-    g = np64(mat.backward(U, S, V, dU, dS, dV))
+    g = np64(mat.backward(dU, dS, dV))
+    assert np.abs(np64(mat.adjoint(U, S, V, dU, dS, dV)) - g).max() <= 1e-6 * np.abs(g).max()
     ref = oracle.svd_adjoint_values(np64(U), np64(S), np64(V), np64(dU), np64(dS), np64(dV), rows, A.col,
                                     center=True)
     err = np.abs(g - ref).max() / np.abs(ref).max()
