@@ -195,6 +195,19 @@ int frpca_gram(frpca_t h, int64_t rows, int l, const float* X, int ldx, double* 
  * Allocates and frees a device scratch buffer of about 266 KiB per call. */
 int frpca_eig(frpca_t h, int l, const double* G, double* W, double* d);
 
+/* frpca_eig_noalloc - the decomposition of frpca_eig without any device allocation, for
+ * callers that cannot allocate (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc). Same kernels and results as frpca_eig (bitwise). Needs no handle:
+ * the work is enqueued on `stream` (hipStream_t as void*, NULL = default stream) and the call
+ * returns without synchronising. Its scratch is a static device buffer of 288 KiB that every
+ * GPU the library runs on holds until the process ends (its address is looked up on the
+ * first call on each device). All calls on one GPU share that buffer: calls whose work
+ * overlaps on one GPU (concurrent streams, or threads) race and must be serialised by the
+ * caller; consecutive calls on one stream are safe. G, W, d: device pointers as in frpca_eig,
+ * 1 <= l <= 128. Errors: EINVAL (l outside 1..128, NULL pointer), EHIP; the message goes to
+ * frpca_last_error(NULL). */
+int frpca_eig_noalloc(int l, const double* G, double* W, double* d, void* stream);
+
 /* eigSVD basis (Alg. 2): Q = X V diag(1/S) with S ascending; S_j <= tol * max(S) gives a
  * zero column (tol <= 0 selects 1e-12). The Gram follows opts.gram_f32 as frpca_gram.
  * X, Q: device float panels (rows x l), S: device double[l] (ascending, zeroed where

@@ -60,6 +60,7 @@ _SIGNATURES = {
     "frpca_spmm": (c_int, [c_void_p, c_int, c_int, c_void_p, c_int, c_int, c_void_p, c_int, c_int]),
     "frpca_gram": (c_int, [c_void_p, c_int64, c_int, c_void_p, c_int, c_void_p]),
     "frpca_eig": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p]),
+    "frpca_eig_noalloc": (c_int, [c_int, c_void_p, c_void_p, c_void_p, c_void_p]),
     "frpca_eigsvd": (c_int, [c_void_p, c_int64, c_int, c_void_p, c_int, c_void_p, c_int, c_void_p, c_double]),
     "frpca_lu": (c_int, [c_void_p, c_int64, c_int, c_void_p, c_int, c_void_p, c_int, c_double, POINTER(c_int)]),
     "frpca_tsmm": (c_int, [c_void_p, c_int64, c_int, c_int, c_void_p, c_int, c_void_p, c_void_p, c_int]),
@@ -166,6 +167,10 @@ def frpca_gram(h, rows, l, X, ldx, G):
 
 def frpca_eig(h, l, G, W, d):
     _check(load().frpca_eig(h, l, _ptr(G), _ptr(W), _ptr(d)), h)
+
+
+def frpca_eig_noalloc(l, G, W, d, stream=None):
+    _check(load().frpca_eig_noalloc(l, _ptr(G), _ptr(W), _ptr(d), stream))
 
 
 def frpca_eigsvd(h, rows, l, X, ldx, Q, ldq, S, tol=0.0):

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -944,6 +945,54 @@ int frpca_export_csc(frpca_t h, int64_t* col_ptr, int32_t* row, int32_t* perm) {
     }
     check_launch();
     FRPCA_HIP(hipStreamSynchronize(st));
+  });
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- allocation-free eig
+namespace {
+
+// Device scratch of frpca_eig_noalloc: the reflectors, the cluster solves' columns and the
+// hand-over state of the three eigensolver kernels. One copy lives on every GPU the library
+// runs on, for the life of the process. Host code never passes this name to a kernel (on the
+// host it is only a stand-in for the symbol); it uses the address looked up per device below.
+constexpr size_t kNoallocScratchBytes = 288 * 1024;
+__device__ __align__(256) char scratch[kNoallocScratchBytes];
+
+constexpr int kMaxDevices = 256;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per device.
+void* noalloc_scratch() {
+  int dev = -1;
+  FRPCA_HIP(hipGetDevice(&dev));
+  FRPCA_CHECK(dev >= 0 && dev < kMaxDevices, FRPCA_EINVAL, "device index outside the supported range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    FRPCA_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    FRPCA_CHECK(p != nullptr, FRPCA_EHIP, "hipGetSymbolAddress returned no address for the eig scratch");
+    g_scratch_dev[dev] = p;
+  }
+  return g_scratch_dev[dev];
+}
+
+}  // namespace
+
+extern "C" {
+
+int frpca_eig_noalloc(int l, const double* G, double* W, double* d, void* stream) {
+  return guarded(nullptr, [&] {
+    FRPCA_CHECK(l >= 1 && l <= kMaxL, FRPCA_EINVAL,
+                "l = " + std::to_string(l) + " is outside 1..128, the range the static eig scratch holds");
+    FRPCA_CHECK(G && W && d, FRPCA_EINVAL, "NULL G, W or d");
+    FRPCA_CHECK(eig_scratch_bytes() <= kNoallocScratchBytes, FRPCA_EHIP,
+                "eigensolver scratch larger than the static buffer");
+    double* buf = static_cast<double*>(noalloc_scratch());
+    launch_eig(G, l, l, d, W, buf, static_cast<hipStream_t>(stream));
+    check_launch();
   });
 }
 
