@@ -7,7 +7,9 @@ k = 100, s = 20, q = 5 passes, inputs resident in HBM. One step = one frpca_run 
 all passes, LU and eigSVD bases, final Rayleigh-Ritz, sign convention). Beside it: q = 3 and 7
 on the same matrix, the BF16-panel and FP32-Gram variants, the 1M x 200K power-law workload,
 the differentiated workload (500K x 100K, k = 50, q = 4) with its forward + backward time
-through the autograd function, and the FP64 CPU oracle on the whole headline job. Prints one
+through the autograd function, the basic randomized algorithm (Alg. 1 / Alg. 4 with QR) against
+the fast one on the paper's Table 2 and Table 4 structures, and the FP64 CPU oracle on the whole
+headline job. Prints one
 JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
@@ -385,6 +387,56 @@ def differentiated(args, torch, np):
     return rec
 
 
+def time_call(fn, reps, torch):
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        out = fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps, out
+
+
+def basic_vs_fast(torch, np, head_mat=None, head_A=None):
+    """The paper's speedup of the fast algorithm over the basic one (Sp1), measured on this GPU.
+
+    Table 2 structure: the ratings stand-in for Matrix 2 (90,230 x 45,115, 24 per row), k = 100,
+    s = 5, Alg. 1 with p = floor((q - 1) / 2) power steps against Alg. 6 with q = 2, 4, 6, 9, 11
+    passes. Table 4 structure on the headline matrix: Alg. 1 with p = 5 against Alg. 6 with
+    q = 12 (k = 100, s = 5). Each line gives both times, Sp1 and the relative difference of
+    the singular values (zero in exact arithmetic for even q by Theorems 1 and 2 when the
+    basic algorithm is Alg. 4; Alg. 1 sketches the other side)."""
+    from paper_1810_06825_amd import FrPCA
+    from synth import ratings_zipf
+
+    A = ratings_zipf()
+    k, s = 100, 5
+    mat = FrPCA.from_csr(A, device="cuda:0")
+    rows = []
+    for q in (2, 4, 6, 9, 11):
+        p = (q - 1) // 2
+        tb, (_, Sb, _) = time_call(lambda: mat.run_basic(k, p, s, SEED, 1), 5, torch)
+        tf, (_, Sf, _) = time_call(lambda: mat.run(k, q, s, SEED), 5, torch)
+        t4, (_, S4, _) = time_call(lambda: mat.run_basic(k, p, s, SEED, 4), 5, torch)
+        Sb, Sf, S4 = (x.double().cpu().numpy() for x in (Sb, Sf, S4))
+        rows.append({"q": q, "p": p, "ms_alg1": round(tb, 3), "ms_alg4": round(t4, 3), "ms_alg6": round(tf, 3),
+                     "sp1_alg1_over_alg6": round(tb / tf, 2), "sp1_alg4_over_alg6": round(t4 / tf, 2),
+                     "sigma_rel_diff_alg4_vs_alg6": float(np.max(np.abs(S4 - Sf) / Sf))})
+        log(f"basic vs fast q={q}:", rows[-1])
+    mat.close()
+    out = {"workload": f"ratings_zipf {A.m}x{A.n} CSR, {A.nnz} nnz", "k": k, "s": s, "table2": rows}
+    if head_mat is not None:
+        tb, _ = time_call(lambda: head_mat.run_basic(k, 5, s, SEED, 1), 2, torch)
+        tf, _ = time_call(lambda: head_mat.run(k, 12, s, SEED), 2, torch)
+        out["table4"] = {"workload": f"{head_A.meta.get('workload')} {head_A.m}x{head_A.n}", "k": k, "s": s,
+                         "ms_alg1_p5": round(tb, 3), "ms_alg6_q12": round(tf, 3), "sp1": round(tb / tf, 2)}
+        log("basic vs fast, headline matrix:", out["table4"])
+    free(torch)
+    return out
+
+
 def cpu_baseline_full(A, k, q, s, factors, np):
     """The FP64 oracle on the whole headline job, timed on the host, and the GPU's error
     against it (singular values, and the subspace of V)."""
@@ -444,12 +496,14 @@ def main():
     ms = h["ms"]
     extras = {}
     var = {}
+    basic = None
     if not args.no_extras:
         for qq in PASS_SWEEP.get(args.workload, ()):
             t, _ = timed_runs(mat, k, qq, s, max(3, args.steps // 2), 1, torch)
             extras[f"ms_q{qq}"] = round(t, 3)
             log(f"q={qq}: {t:.3f} ms")
         var = variants(A, k, q, s, args.steps, torch, np, h["factors"][1])
+        basic = basic_vs_fast(torch, np, mat, A)
     U, S, V = (t.detach() for t in h["factors"])
     S_host, V_host = S.cpu(), V.cpu()
     mat.close()
@@ -496,6 +550,7 @@ def main():
         "variants": var or None,
         "zipf_lognormal": secondary,
         "differentiated": diff,
+        "basic_vs_fast": basic,
     }
     print(json.dumps(out), flush=True)
 

@@ -47,7 +47,8 @@ extern "C" {
 #define FRPCA_T_SPMM_COMB 11 /* row-block partials of the transpose product combined   */
 #define FRPCA_T_SPMM_TAIL 12 /* transpose product, columns outside the row-block part  */
 #define FRPCA_T_CENTER 13 /* rank-1 terms of the centred products (opts.center)       */
-#define FRPCA_NTIMERS 14
+#define FRPCA_T_QR 14     /* Cholesky factors and small SVD of the basic algorithms   */
+#define FRPCA_NTIMERS 15
 
 typedef struct frpca_ctx* frpca_t;
 
@@ -132,6 +133,26 @@ int frpca_run(frpca_t h, int k, int p_passes, int s_oversample, uint64_t seed, f
               float* S, float* V);
 
 /*
+ * frpca_run_basic - rank-k truncated SVD by the basic randomized algorithm that frPCA
+ * accelerates: Alg. 1 (basic rPCA, Section 2.2; alg = 1) or Alg. 4 (basic rPCAt, Section
+ * 3.2; alg = 4), for any shape of A, with p_power >= 0 power steps (2 p_power + 2 passes
+ * over A). Every product with A or A^T is followed by orth(), here CholeskyQR2 (FP64 Gram on
+ * the matrix cores, FP64 Cholesky with a rank guard, Q = X R^-1, twice), which by Lemma 2
+ * gives the algorithm the result of the paper's Householder QR; the final svd(B) is the
+ * CholeskyQR2 factor R of B^T followed by a one-sided Jacobi SVD of R in FP64. Gaussian
+ * matrix: Alg. 1 draws Omega as n x l, Alg. 4 draws its l x m Omega stored as m x l (element
+ * [r, j] = normal(seed, r*l + j), the draws of frpca_run for odd / even q), so by Theorems 1
+ * and 2 the result equals frpca_run with q = 2 p_power + 2 on the matching orientation (Alg. 5
+ * from Alg. 1 when m < n, Alg. 6 from Alg. 4 when m >= n). Outputs, rank and sign conventions
+ * as frpca_run. frpca_backward does not apply to this path (ESTATE afterwards). The first
+ * call allocates a second long-side panel in the handle's workspace.
+ * Errors: EINVAL (k < 1, s < 0, k+s > min(m,n), k+s > 128, p_power < 0, alg not 1 or 4),
+ * ENOMEM, EHIP.
+ */
+int frpca_run_basic(frpca_t h, int k, int p_power, int s_oversample, uint64_t seed, int alg, float* U,
+                    float* S, float* V);
+
+/*
  * frpca_backward - dL/d(values of A) from dL/dU, dL/dS, dL/dV of the handle's last frpca_run,
  * through the truncated-SVD adjoint projected onto the sparsity pattern (not part of the
  * paper; the standard SVD reverse-mode rule): with J = U^T dU, K = V^T dV (FP64),
@@ -214,6 +235,19 @@ int frpca_eig_noalloc(int l, const double* G, double* W, double* d, void* stream
  * dropped). */
 int frpca_eigsvd(frpca_t h, int64_t rows, int l, const float* X, int ldx, float* Q, int ldq,
                  double* S, double tol);
+
+/* orth() of the basic algorithms: Q = X R^-1 with R the CholeskyQR2 factor of X (rows x l,
+ * rows >= l); a column whose Cholesky pivot is <= 1e-13 of its squared norm in either pass is
+ * zero in Q (*ndropped, host int, counts them). R (device double[l*l], upper triangular, may
+ * be NULL) receives R2 R1. */
+int frpca_orth(frpca_t h, int64_t rows, int l, const float* X, int ldx, float* Q, int ldq, double* R,
+               int* ndropped);
+
+/* SVD of a small square matrix by one-sided Jacobi in FP64 (the svd(B) step of the basic
+ * algorithms, applied to the triangular factor of B^T): R (device double[l*l], row-major)
+ * = U_R diag(sqrt(d)) W^T with d (device double[l]) ascending and W (device double[l*l],
+ * row-major, column j paired with d[j]) orthonormal; l <= 128. */
+int frpca_jacobi_svd(frpca_t h, int l, const double* R, double* W, double* d);
 
 /* LU basis (Lemma 3, eq. 8): Q = P^T L of P X = L U with pivots chosen by tournament
  * pivoting (partial pivoting inside each node); pivot rows of Q form a unit lower-triangular

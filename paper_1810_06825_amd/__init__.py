@@ -97,6 +97,24 @@ class FrPCA:
         self.last_k = k
         return U, S, V
 
+    def run_basic(self, k: int, power: int, s: int, seed: int, alg: int, out=None):
+        """Rank-k truncated SVD by the basic randomized algorithm (Alg. 1 with alg = 1, Alg. 4
+        with alg = 4) with `power` power steps and QR orthonormalisation (frpca_run_basic)."""
+        self._sync_stream()
+        if out is None:
+            U = torch.empty((self.m, k), dtype=torch.float32, device=self.device)
+            S = torch.empty((k,), dtype=torch.float32, device=self.device)
+            V = torch.empty((self.n, k), dtype=torch.float32, device=self.device)
+        else:
+            U, S, V = out
+            for t, rows, cols, name in ((U, self.m, k, "U"), (S, k, None, "S"), (V, self.n, k, "V")):
+                self._panel(t, rows, cols, name)
+                if not t.is_contiguous():
+                    raise ValueError(f"{name} must be contiguous (the library writes it in place)")
+        binding.frpca_run_basic(self.h, k, power, s, seed, alg, U, S, V)
+        self.run_id += 1
+        return U, S, V
+
     def _grads(self, k, dU, dS, dV):
         out = []
         for t, rows, cols, name in ((dU, self.m, k, "dU"), (dS, k, None, "dS"), (dV, self.n, k, "dV")):

@@ -17,10 +17,10 @@ FRPCA_EINVAL = -1
 FRPCA_ENOMEM = -2
 FRPCA_EHIP = -3
 FRPCA_ESTATE = -4
-NTIMERS = 14
+NTIMERS = 15
 TIMER_NAMES = ("gauss", "spmm_fwd", "spmm_back", "gram", "eig", "lu", "tsmm", "sign", "bwd", "sddmm",
                "spmm_fixup", "spmm_combine",
-               "spmm_back_tail", "center")
+               "spmm_back_tail", "center", "qr")
 
 
 class FrpcaError(RuntimeError):
@@ -49,6 +49,7 @@ _SIGNATURES = {
     "frpca_set_values": (c_int, [c_void_p, c_void_p]),
     "frpca_set_stream": (c_int, [c_void_p, c_void_p]),
     "frpca_run": (c_int, [c_void_p, c_int, c_int, c_int, c_uint64, c_void_p, c_void_p, c_void_p]),
+    "frpca_run_basic": (c_int, [c_void_p, c_int, c_int, c_int, c_uint64, c_int, c_void_p, c_void_p, c_void_p]),
     "frpca_backward": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "frpca_adjoint": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                               c_void_p]),
@@ -63,6 +64,8 @@ _SIGNATURES = {
     "frpca_eig_noalloc": (c_int, [c_int, c_void_p, c_void_p, c_void_p, c_void_p]),
     "frpca_eigsvd": (c_int, [c_void_p, c_int64, c_int, c_void_p, c_int, c_void_p, c_int, c_void_p, c_double]),
     "frpca_lu": (c_int, [c_void_p, c_int64, c_int, c_void_p, c_int, c_void_p, c_int, c_double, POINTER(c_int)]),
+    "frpca_orth": (c_int, [c_void_p, c_int64, c_int, c_void_p, c_int, c_void_p, c_int, c_void_p, POINTER(c_int)]),
+    "frpca_jacobi_svd": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p]),
     "frpca_tsmm": (c_int, [c_void_p, c_int64, c_int, c_int, c_void_p, c_int, c_void_p, c_void_p, c_int]),
     "frpca_sddmm": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "frpca_export_csc": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
@@ -126,6 +129,10 @@ def frpca_run(h, k, p_passes, s_oversample, seed, U, S, V):
     _check(load().frpca_run(h, k, p_passes, s_oversample, seed, _ptr(U), _ptr(S), _ptr(V)), h)
 
 
+def frpca_run_basic(h, k, p_power, s_oversample, seed, alg, U, S, V):
+    _check(load().frpca_run_basic(h, k, p_power, s_oversample, seed, alg, _ptr(U), _ptr(S), _ptr(V)), h)
+
+
 def frpca_backward(h, dU, dS, dV, dval):
     _check(load().frpca_backward(h, _ptr(dU), _ptr(dS), _ptr(dV), _ptr(dval)), h)
 
@@ -181,6 +188,16 @@ def frpca_lu(h, rows, l, X, ldx, Q, ldq, tol=0.0) -> int:
     nd = c_int(0)
     _check(load().frpca_lu(h, rows, l, _ptr(X), ldx, _ptr(Q), ldq, tol, ctypes.byref(nd)), h)
     return nd.value
+
+
+def frpca_orth(h, rows, l, X, ldx, Q, ldq, R=None) -> int:
+    nd = c_int(0)
+    _check(load().frpca_orth(h, rows, l, _ptr(X), ldx, _ptr(Q), ldq, _ptr(R), ctypes.byref(nd)), h)
+    return nd.value
+
+
+def frpca_jacobi_svd(h, l, R, W, d):
+    _check(load().frpca_jacobi_svd(h, l, _ptr(R), _ptr(W), _ptr(d)), h)
 
 
 def frpca_tsmm(h, rows, kdim, c, X, ldx, B, out, ldo):

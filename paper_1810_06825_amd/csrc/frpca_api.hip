@@ -23,6 +23,9 @@ namespace {
 thread_local std::string g_last_error;
 constexpr double kInnerTol = 1e-12;
 constexpr double kDefaultRankTol = 1e-5;
+// Cholesky pivot guard of orth() in the basic algorithms: a column whose residual norm falls
+// below about 3e-7 of its own norm is numerically dependent on the earlier ones.
+constexpr double kCholTol = 1e-13;
 
 size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
@@ -110,6 +113,12 @@ struct frpca_ctx {
   uint16_t *Qb = nullptr, *Yb = nullptr;
   double *gram_part = nullptr, *G = nullptr, *W = nullptr, *d = nullptr;
   double *B1 = nullptr, *B2 = nullptr;
+  double *R1 = nullptr, *R2 = nullptr, *Rp = nullptr;  // CholeskyQR2 factors (basic algorithms)
+  // second long-side panel of the basic algorithms (their bases may live on the long side)
+  void* ws2 = nullptr;
+  size_t ws2_bytes = 0;
+  int ws2_lp = 0;
+  float* Z2 = nullptr;
   float* Skeep = nullptr;  // singular values of the last run (library copy)
   int *order = nullptr, *ndrop = nullptr;
   double* eig_tmp = nullptr;
@@ -152,6 +161,7 @@ struct frpca_ctx {
     for (void* p : owned) (void)hipFree(p);
     if (ws) (void)hipFree(ws);
     if (bws) (void)hipFree(bws);
+    if (ws2) (void)hipFree(ws2);
   }
 
   void* alloc_owned(size_t bytes) {
@@ -264,6 +274,9 @@ struct frpca_ctx {
       W = a.take<double>(kMaxL * kMaxL);
       B1 = a.take<double>(kMaxL * kMaxL);
       B2 = a.take<double>(kMaxL * kMaxL);
+      R1 = a.take<double>(kMaxL * kMaxL);
+      R2 = a.take<double>(kMaxL * kMaxL);
+      Rp = a.take<double>(kMaxL * kMaxL);
       Skeep = a.take<float>(kMaxL);
       d = a.take<double>(kMaxL);
       order = a.take<int>(kMaxL);
@@ -291,6 +304,53 @@ struct frpca_ctx {
     ws_bytes = need;
     ws_lp = lp;
     ws_bf16 = bf16;
+  }
+
+  void ensure_long2(int lp) {
+    if (ws2 && ws2_lp >= lp) return;
+    if (ws2) {
+      FRPCA_HIP(hipStreamSynchronize(stream));
+      FRPCA_HIP(hipFree(ws2));
+      ws2 = nullptr;
+      ws2_bytes = 0;
+    }
+    const size_t need = align256((size_t)long_rows() * lp * sizeof(float));
+    if (opts.max_workspace && need + ws_bytes + setup_bytes > opts.max_workspace)
+      throw Error{FRPCA_ENOMEM, "second long-side panel of " + std::to_string(need) + " bytes exceeds opts.max_workspace"};
+    if (hipMalloc(&ws2, need) != hipSuccess) {
+      (void)hipGetLastError();
+      ws2 = nullptr;
+      throw Error{FRPCA_ENOMEM, "long-side panel allocation of " + std::to_string(need) + " bytes failed"};
+    }
+    ws2_bytes = need;
+    ws2_lp = lp;
+    Z2 = static_cast<float*>(ws2);
+  }
+
+  // orth() of the basic algorithms on a panel (rows x l, ld lp) in place, through tmp:
+  // CholeskyQR2. With Rout, also R = R2 R1 (the triangular factor of the panel).
+  void orth_cqr2(float* P, float* tmp, int64_t rows, int l, int lp, double* Rout, hipStream_t st) {
+    for (int pass = 0; pass < 2; ++pass) {
+      const float* in = pass == 0 ? P : tmp;
+      float* out = pass == 0 ? tmp : P;
+      double* Bc = pass == 0 ? B1 : B2;
+      double* Rc = pass == 0 ? R1 : R2;
+      {
+        Scope t(this, FRPCA_T_GRAM);
+        launch_gram(in, false, lp, nullptr, 0, rows, l, gram_part, G, l, st, false);
+      }
+      {
+        Scope t(this, FRPCA_T_QR);
+        launch_chol_inv(G, l, l, kCholTol, Bc, lp, Rout ? Rc : nullptr, nullptr, st);
+      }
+      if (Rout && pass == 1) {
+        Scope t(this, FRPCA_T_QR);
+        launch_small_matmul(R2, R1, l, Rout, st);
+        return;  // the factor is all the SVD step needs
+      }
+      Scope t(this, FRPCA_T_TSMM);
+      launch_tsmm(in, false, lp, rows, l, Bc, lp, l, lp, out, lp, nullptr, 0, st);
+    }
   }
 };
 
@@ -645,6 +705,106 @@ int frpca_run(frpca_t h, int k, int p_passes, int s_oversample, uint64_t seed, f
   });
 }
 
+int frpca_run_basic(frpca_t h, int k, int p_power, int s_oversample, uint64_t seed, int alg, float* U, float* S,
+                    float* V) {
+  if (!h) return fail(nullptr, Error{FRPCA_EINVAL, "NULL handle"});
+  return guarded(h, [&] {
+    const int64_t m = h->m, n = h->n;
+    FRPCA_CHECK(k >= 1 && s_oversample >= 0, FRPCA_EINVAL, "need k >= 1 and s >= 0");
+    const int l = k + s_oversample;
+    FRPCA_CHECK(l <= std::min(m, n), FRPCA_EINVAL, "need k + s <= min(m, n)");
+    FRPCA_CHECK(l <= kMaxL, FRPCA_EINVAL, "need k + s <= 128");
+    FRPCA_CHECK(p_power >= 0, FRPCA_EINVAL, "the power parameter p must be >= 0");
+    FRPCA_CHECK(alg == 1 || alg == 4, FRPCA_EINVAL, "alg must be 1 (basic rPCA) or 4 (basic rPCAt)");
+    FRPCA_CHECK(!h->opts.center, FRPCA_EINVAL, "the centred products apply to frpca_run only");
+    FRPCA_CHECK(U && S && V, FRPCA_EINVAL, "NULL output");
+    const int LP = panel_ld(l);
+    h->saved_k = 0;
+    h->ensure_workspace(LP, h->opts.panel_bf16 ? 1 : 0);
+    h->ensure_long2(LP);
+    hipStream_t st = h->stream;
+    const bool a6 = m >= n;
+    const MergePlan& Fp = a6 ? h->csr : h->csc;  // short side -> long side
+    const MergePlan& Bp = a6 ? h->csc : h->csr;  // long side -> short side
+    const int64_t Ns = h->short_rows(), Nl = h->long_rows();
+    auto spmm = [&](const MergePlan& p, int cls, const float* in, float* out) {
+      {
+        frpca_ctx::Scope t(h, cls);
+        launch_spmm_main(p, LP, in, false, LP, out, nullptr, LP, st);
+      }
+      frpca_ctx::Scope t(h, FRPCA_T_SPMM_FIX);
+      launch_spmm_fixup(p, LP, out, nullptr, LP, st);
+    };
+    auto forward = [&](const float* in, float* out) { spmm(Fp, FRPCA_T_SPMM_F, in, out); };
+    auto back = [&](const float* in, float* out) {
+      if (a6 && h->has_bcsc) {
+        spmm(h->bhotp, FRPCA_T_SPMM_B, in, h->bpart);
+        spmm(h->btailp, FRPCA_T_SPMM_TAIL, in, out);
+        frpca_ctx::Scope t(h, FRPCA_T_SPMM_COMB);
+        launch_bcsc_combine(h->bpart, LP, h->bhotcol, h->bhot, h->bnblk, LP, out, nullptr, LP, st);
+      } else {
+        spmm(Bp, FRPCA_T_SPMM_B, in, out);
+      }
+    };
+    // The basis Q lives on side S (the m side for Alg. 1, the n side for Alg. 4), the Gaussian
+    // matrix and G on the other side O. Each side has a panel and a scratch panel for orth().
+    const bool s_short = (alg == 4) == a6;
+    const int64_t NS = s_short ? Ns : Nl, NO = s_short ? Nl : Ns;
+    float* S1 = s_short ? h->Q : h->Z;
+    float* S2 = s_short ? h->X : h->Z2;
+    float* O1 = s_short ? h->Z : h->Q;
+    float* O2 = s_short ? h->Z2 : h->X;
+    auto to_S = [&](const float* in, float* out) { s_short ? back(in, out) : forward(in, out); };
+    auto to_O = [&](const float* in, float* out) { s_short ? forward(in, out) : back(in, out); };
+
+    {
+      frpca_ctx::Scope t(h, FRPCA_T_GAUSS);  // Omega: n x l (Alg. 1), or l x m stored m x l (Alg. 4)
+      launch_gaussian(seed, NO, l, LP, O1, nullptr, st);
+    }
+    to_S(O1, S1);
+    h->orth_cqr2(S1, S2, NS, l, LP, nullptr, st);
+    for (int i = 0; i < p_power; ++i) {
+      to_O(S1, O1);
+      h->orth_cqr2(O1, O2, NO, l, LP, nullptr, st);
+      to_S(O1, S1);
+      h->orth_cqr2(S1, S2, NS, l, LP, nullptr, st);
+    }
+    // B^T = (the product of Q back to side O); svd(B) from the CholeskyQR2 factor of B^T
+    to_O(S1, O1);
+    h->orth_cqr2(O1, O2, NO, l, LP, h->Rp, st);
+    {
+      frpca_ctx::Scope t(h, FRPCA_T_QR);
+      launch_jacobi_svd(h->Rp, l, l * 2.220446049250313e-16, h->d, h->W, st);
+    }
+    // B^T W = (left singular vectors of B^T) diag(sigma): the O-side factor is B^T W / sigma,
+    // the S-side factor is Q W (the k largest, largest first)
+    double* Bo = h->B1;
+    double* Bs = h->B2;
+    launch_final_coeffs(h->d, h->W, l, k, LP, h->rank_tol, Bo, Bs, S, h->Skeep, h->ndrop, st);
+    const bool u_on_S = alg == 1;  // the m side is S for Alg. 1
+    float* Pu = u_on_S ? S1 : O1;
+    float* Pv = u_on_S ? O1 : S1;
+    double* Bu = u_on_S ? Bs : Bo;
+    double* Bv = u_on_S ? Bo : Bs;
+    {
+      frpca_ctx::Scope t(h, FRPCA_T_TSMM);
+      launch_tsmm(Pv, false, LP, n, l, Bv, LP, k, k, V, k, nullptr, 0, st);
+    }
+    if (!h->opts.no_sign_fix) {
+      frpca_ctx::Scope t(h, FRPCA_T_SIGN);
+      launch_sign_fix(V, n, k, Bu, Bv, LP, l, h->sign_tmp, st);
+    }
+    {
+      frpca_ctx::Scope t(h, FRPCA_T_TSMM);
+      launch_tsmm(Pu, false, LP, m, l, Bu, LP, k, k, U, k, nullptr, 0, st);
+    }
+    check_launch();
+    h->info.k = k;
+    h->info.s = s_oversample;
+    h->info.passes = 2 * p_power + 2;
+  });
+}
+
 // Adjoint at the factors (U m x k, S, V n x k), projected on the pattern. With `saved` the
 // factors are the last run's, rebuilt from the library's panels; otherwise they are the
 // caller's (leading dimension k). Every panel of the adjoint has leading dimension k rounded
@@ -785,7 +945,7 @@ int frpca_get_info(frpca_t h, frpca_info* info) {
       FRPCA_HIP(hipStreamSynchronize(h->stream));
       h->info.rank_dropped = nd;
     }
-    h->info.workspace_bytes = h->setup_bytes + h->ws_bytes + h->bws_bytes;
+    h->info.workspace_bytes = h->setup_bytes + h->ws_bytes + h->bws_bytes + h->ws2_bytes;
     *info = h->info;
   });
 }
@@ -886,6 +1046,46 @@ int frpca_eigsvd(frpca_t h, int64_t rows, int l, const float* X, int ldx, float*
     launch_tsmm(X, false, ldx, rows, l, B, l, l, l, Q, ldq, nullptr, 0, st);
     check_launch();
     FRPCA_HIP(hipStreamSynchronize(st));
+  });
+}
+
+int frpca_orth(frpca_t h, int64_t rows, int l, const float* X, int ldx, float* Q, int ldq, double* R,
+               int* ndropped) {
+  if (!h) return fail(nullptr, Error{FRPCA_EINVAL, "NULL handle"});
+  return guarded(h, [&] {
+    FRPCA_CHECK(rows >= l && l >= 1 && l <= kMaxL && ldx >= l && ldq >= l && X && Q, FRPCA_EINVAL,
+                "bad orth arguments (need rows >= l)");
+    hipStream_t st = h->stream;
+    DeviceTemp part(gram_partial_bytes(l)), misc(6 * kMaxL * kMaxL * sizeof(double)), tmp((size_t)rows * ldq * 4),
+        nd(256);
+    double* G = static_cast<double*>(misc.p);
+    double* B1 = G + kMaxL * kMaxL;
+    double* B2 = B1 + kMaxL * kMaxL;
+    double* R1 = B2 + kMaxL * kMaxL;
+    double* R2 = R1 + kMaxL * kMaxL;
+    float* T = static_cast<float*>(tmp.p);
+    launch_gram(X, false, ldx, nullptr, 0, rows, l, static_cast<double*>(part.p), G, l, st, false);
+    launch_chol_inv(G, l, l, kCholTol, B1, l, R1, nullptr, st);
+    launch_tsmm(X, false, ldx, rows, l, B1, l, l, ldq, T, ldq, nullptr, 0, st);
+    launch_gram(T, false, ldq, nullptr, 0, rows, l, static_cast<double*>(part.p), G, l, st, false);
+    launch_chol_inv(G, l, l, kCholTol, B2, l, R2, static_cast<int*>(nd.p), st);
+    launch_tsmm(T, false, ldq, rows, l, B2, l, l, ldq, Q, ldq, nullptr, 0, st);
+    if (R) launch_small_matmul(R2, R1, l, R, st);
+    check_launch();
+    int hnd = 0;
+    FRPCA_HIP(hipMemcpyAsync(&hnd, nd.p, sizeof(int), hipMemcpyDeviceToHost, st));
+    FRPCA_HIP(hipStreamSynchronize(st));
+    if (ndropped) *ndropped = hnd;
+  });
+}
+
+int frpca_jacobi_svd(frpca_t h, int l, const double* R, double* W, double* d) {
+  if (!h) return fail(nullptr, Error{FRPCA_EINVAL, "NULL handle"});
+  return guarded(h, [&] {
+    FRPCA_CHECK(l >= 1 && l <= kMaxL && R && W && d, FRPCA_EINVAL, "bad Jacobi SVD arguments");
+    launch_jacobi_svd(R, l, l * 2.220446049250313e-16, d, W, h->stream);
+    check_launch();
+    FRPCA_HIP(hipStreamSynchronize(h->stream));
   });
 }
 

@@ -383,7 +383,10 @@ __device__ __forceinline__ void spmm_partition4(const SpmmArgs& a, int64_t w, in
 }
 
 template <bool IN_BF16>
-__global__ __launch_bounds__(256) void spmm_merge4_kernel(SpmmArgs a) {
+#ifndef FRPCA_SPMM_MINW
+#define FRPCA_SPMM_MINW 1
+#endif
+__global__ __launch_bounds__(256, FRPCA_SPMM_MINW) void spmm_merge4_kernel(SpmmArgs a) {
   __shared__ int win[4][128];  // per wave: 64 segment ends, then 64 output rows
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);

@@ -148,6 +148,18 @@ size_t lu_temp_bytes(int64_t rows, int l);
 void launch_lu_coeffs(const float* X, int ldx, int64_t rows, int l, double tol, double* B,
                       int ldb, void* temp, int* ndropped_dev, hipStream_t st);
 
+// ---------------------------------------------------------------- basic rPCA (k_qr.hip)
+// Cholesky G = R^T R of an l x l FP64 Gram matrix (ldg) and R^-1 as TSMM coefficients Binv
+// (l x ldb, zero padded); a pivot <= tol * G_jj drops column j (zero row of R, zero column
+// of R^-1). R (l x l, ld l) and ndrop (device int) are optional outputs.
+void launch_chol_inv(const double* G, int ldg, int l, double tol, double* Binv, int ldb, double* R, int* ndrop,
+                     hipStream_t st);
+// C = A B for l x l FP64 matrices (ld l).
+void launch_small_matmul(const double* A, const double* B, int l, double* C, hipStream_t st);
+// One-sided Jacobi SVD of R (l x l, ld l): d = sigma^2 ascending, W (l x l row-major) the
+// right singular vectors of R paired with d (the layout of launch_eig).
+void launch_jacobi_svd(const double* R, int l, double tol, double* d, double* W, hipStream_t st);
+
 // ---------------------------------------------------------------- adjoint
 // From J = U^T dU, K = V^T dV (k x k, FP64, ld k) and S, dS: coefficient matrices
 // CU = M - J S+, CV = -K S+, SP = diag(S+) (k x k, FP64, ld k).

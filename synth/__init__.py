@@ -11,6 +11,7 @@ from .matrices import (  # noqa: F401
     aminer_tfidf,
     zipf_normal,
     planted_blocks,
+    ratings_zipf,
     from_dense,
     random_sparse,
     WORKLOADS,

@@ -247,6 +247,16 @@ def zipf_normal(m: int = 500_000, n: int = 100_000, t: int = 30, alpha: float = 
     return Csr(m, n, row_ptr, col, val, {"workload": "zipf_normal"})
 
 
+def ratings_zipf(m: int = 90_230, n: int = 45_115, t: int = 24, alpha: float = 1.1, seed: int = 1006) -> Csr:
+    """User x item ratings stand-in (the shape and density of the paper's Matrix 2, a
+    MovieLens matrix thinned to 24 nonzeros per row): Zipf(1.1) item popularity, integer
+    ratings 1..5 with probabilities 0.06, 0.11, 0.27, 0.34, 0.22."""
+    row_ptr, col = zipf_rows(m, n, t, alpha, seed)
+    rng = np.random.default_rng(seed + 50_000)
+    val = rng.choice(np.arange(1, 6, dtype=np.float32), size=col.size, p=[0.06, 0.11, 0.27, 0.34, 0.22])
+    return Csr(m, n, row_ptr, col, val.astype(np.float32), {"workload": "ratings_zipf"})
+
+
 def planted_blocks(m: int = 200_000, n: int = 50_000, blocks: int = 200, seed: int = 1005,
                    decades: float = 3.0) -> Csr:
     """Block-disjoint planted spectrum: A = sum_i sigma_i u_i v_i^T, sigma_i = 10^(-3i/B).
@@ -290,4 +300,5 @@ WORKLOADS = {
     "aminer_tfidf": (aminer_tfidf, {}, 100, 20, 5),
     "zipf_normal": (zipf_normal, {}, 50, 10, 4),
     "planted_blocks": (planted_blocks, {}, 100, 20, 5),
+    "ratings_zipf": (ratings_zipf, {}, 100, 5, 11),
 }
