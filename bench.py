@@ -8,8 +8,8 @@ all passes, LU and eigSVD bases, final Rayleigh-Ritz, sign convention). Beside i
 on the same matrix, the BF16-panel and FP32-Gram variants, the 1M x 200K power-law workload,
 the differentiated workload (500K x 100K, k = 50, q = 4) with its forward + backward time
 through the autograd function, the basic randomized algorithm (Alg. 1 / Alg. 4 with QR) against
-the fast one on the paper's Table 2 and Table 4 structures, and the FP64 CPU oracle on the whole
-headline job. Prints one
+the fast one on the paper's Table 2 and Table 4 structures, eigSVDs (Alg. 3) against both on its
+Table 3 structure, and the FP64 CPU oracle on the whole headline job. Prints one
 JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
@@ -258,14 +258,16 @@ def headline(args, A, k, q, s, torch, np):
 
 
 def variants(A, k, q, s, steps, torch, np, S_ref):
-    """BF16 panels, the FP32-MFMA Gram and the centred run on the headline matrix: time and
+    """BF16 panels (every inner pass pair, or all but the last one), the FP32-MFMA Gram, the
+    one-sweep pass pairs with atomic adds and the centred run on the headline matrix: time and
     singular-value difference against the default FP32 path."""
     from paper_1810_06825_amd import FrPCA
 
     out = {}
     Sf = S_ref.double().cpu().numpy()
     n = max(3, steps // 2)
-    for name, kw in (("bf16_panel", {"panel_bf16": True}), ("gram_f32", {"gram_f32": True}),
+    for name, kw in (("bf16_panel", {"panel_bf16": 1}), ("bf16_mixed", {"panel_bf16": 2}),
+                     ("gram_f32", {"gram_f32": True}), ("fused_pass", {"fused_pass": True}),
                      ("centered", {"center": True})):
         m2 = FrPCA.from_csr(A, device="cuda:0", **kw)
         t, (_, S2, _) = timed_runs(m2, k, q, s, n, 1, torch)
@@ -280,6 +282,8 @@ def variants(A, k, q, s, steps, torch, np, S_ref):
             rec["S"] = S2.double().cpu().numpy()
         if name == "gram_f32":
             rec["gram_ms"] = round(inf["t_ms"]["gram"] / n, 4)
+        if name == "fused_pass":
+            rec["pass_pairs_ms"] = round(inf["t_ms"]["spmm_fwd"] / n, 4)
         if name == "centered":
             rec["rank1_terms_ms"] = round(inf["t_ms"]["center"] / n, 4)
         log(f"variant {name}: {t:.3f} ms", {kk: v for kk, v in rec.items() if kk != "S"})
@@ -298,12 +302,22 @@ def secondary_zipf(args, torch, np):
     A = gen(**kw)
     l = k + s
     mat = FrPCA.from_csr(A, device="cuda:0")
-    ms, _ = timed_runs(mat, k, q, s, args.steps, args.warmup, torch)
+    ms, (_, S0, _) = timed_runs(mat, k, q, s, args.steps, args.warmup, torch)
+    S0 = S0.double().cpu().numpy()
     rec = {"workload": f"zipf_lognormal {A.m}x{A.n} CSR, {A.nnz} nnz", "k": k, "s": s, "ms_q5": round(ms, 3)}
     for qq in (4, 6):
         t, _ = timed_runs(mat, k, qq, s, max(3, args.steps // 2), 1, torch)
         rec[f"ms_q{qq}"] = round(t, 3)
     mat.close()
+    # the precision and fusion variants on this matrix: time and sigma difference against FP32
+    rec["variants"] = {}
+    for name, vkw in (("bf16_panel", {"panel_bf16": 1}), ("bf16_mixed", {"panel_bf16": 2}),
+                      ("fused_pass", {"fused_pass": True})):
+        mv = FrPCA.from_csr(A, device="cuda:0", **vkw)
+        t, (_, Sv, _) = timed_runs(mv, k, q, s, max(3, args.steps // 2), 1, torch)
+        mv.close()
+        Sv = Sv.double().cpu().numpy()
+        rec["variants"][name] = {"ms": round(t, 3), "sigma_rel_diff_vs_fp32": float(np.max(np.abs(Sv - S0) / S0))}
     matt = FrPCA.from_csr(A, device="cuda:0", timing=True)
     timed_runs(matt, k, q, s, max(3, args.steps // 2), 1, torch)
     info = matt.info()
@@ -437,6 +451,43 @@ def basic_vs_fast(torch, np, head_mat=None, head_A=None):
     return out
 
 
+def eigsvds_vs_fast(torch, np):
+    """Table 3 structure (the paper's Matrix 7: a 647,989 x 107,966 slice of the Aminer matrix
+    with a few nonzeros per row): eigSVDs (Alg. 3, k = 100, block of 128, converged to
+    ||B w - theta w|| <= 1e-6 theta_max) against Alg. 6 (q = 11) and Alg. 1 (p = 5), s = 5 for
+    the randomized ones as in the paper; times, eigSVDs' iterations and the singular-value
+    differences between the three."""
+    from paper_1810_06825_amd import FrPCA
+    from synth import aminer_tfidf
+
+    A = aminer_tfidf(m=647_989, n=107_966, t=4, seed=1007)
+    mat = FrPCA.from_csr(A, device="cuda:0")
+    k = 100
+    te, (_, Se, _, it) = time_call(lambda: mat.eigsvds(k, 28, SEED), 2, torch)
+    tf, (_, Sf, _) = time_call(lambda: mat.run(k, 11, 5, SEED), 3, torch)
+    tb, (_, Sb, _) = time_call(lambda: mat.run_basic(k, 5, 5, SEED, 1), 3, torch)
+    _, Se, Ve, _ = mat.eigsvds(k, 28, SEED)
+    _, Sf, Vf = mat.run(k, 11, 5, SEED)
+    Se, Sf, Sb = (x.double().cpu().numpy() for x in (Se, Sf, Sb))
+    Ve, Vf = Ve.double().cpu().numpy(), Vf.double().cpu().numpy()
+    mat.close()
+    free(torch)
+    # how well each result solves A^T A v = sigma^2 v (FP64 on the host, relative to sigma_1^2)
+    Asp = A.to_scipy()
+
+    def resid(S, V):
+        R = Asp.T @ (Asp @ V) - V * S ** 2
+        return float(np.max(np.linalg.norm(R, axis=0)) / S[0] ** 2)
+
+    out = {"workload": f"aminer_tfidf {A.m}x{A.n} CSR, {A.nnz} nnz (seed 1007)", "k": k,
+           "ms_eigsvds": round(te, 3), "eigsvds_iterations": it, "ms_alg6_q11": round(tf, 3),
+           "ms_alg1_p5": round(tb, 3), "sigma_rel_diff_alg6_vs_eigsvds": float(np.max(np.abs(Sf - Se) / Se)),
+           "sigma_rel_diff_alg1_vs_eigsvds": float(np.max(np.abs(Sb - Se) / Se)),
+           "max_residual_eigsvds": resid(Se, Ve), "max_residual_alg6_q11": resid(Sf, Vf)}
+    log("eigSVDs vs fast:", out)
+    return out
+
+
 def cpu_baseline_full(A, k, q, s, factors, np):
     """The FP64 oracle on the whole headline job, timed on the host, and the GPU's error
     against it (singular values, and the subspace of V)."""
@@ -509,10 +560,11 @@ def main():
     mat.close()
     del U, S, V, h["factors"]
     free(torch)
-    secondary = diff = None
+    secondary = diff = eigs = None
     if not args.no_extras:
         secondary = secondary_zipf(args, torch, np)
         diff = differentiated(args, torch, np)
+        eigs = eigsvds_vs_fast(torch, np)
     cpu = None
     So = None
     if args.cpu_baseline == "full":
@@ -551,6 +603,7 @@ def main():
         "zipf_lognormal": secondary,
         "differentiated": diff,
         "basic_vs_fast": basic,
+        "eigsvds_vs_fast": eigs,
     }
     print(json.dumps(out), flush=True)
 

@@ -57,7 +57,12 @@ typedef struct {
   int panel_bf16;       /* 1: inner-pass panels (the basis fed to the forward product and
                            the long-side panel fed to the back product) are stored in BF16
                            (round to nearest even) with FP32 accumulation; the final pass
-                           reads the FP32 basis. 0 (default): FP32 panels.            */
+                           reads the FP32 basis. 2: the same except in the last inner pass
+                           pair (the one before the final eigSVD basis), which stays FP32,
+                           so a BF16 rounding only perturbs the starting subspace of a pass
+                           pair that follows. 3: only the basis read by the inner forward
+                           products is stored in BF16 (the long-side panel stays FP32).
+                           0 (default): FP32 panels.                                   */
   int no_sign_fix;      /* 0 (default): flip each (u_i, v_i) so that the largest-|.| entry
                            of v_i is positive (ties: lowest index). 1: leave signs.      */
   double rank_tol;      /* singular values <= rank_tol * sigma_max of the final eigSVD
@@ -78,6 +83,13 @@ typedef struct {
                            (u32 = 2^-24: half the 16-row sum times unit roundoff).
                            0 (default): FP64 matrix cores on the FP32 panels, each product
                            exact and only the FP64 sums rounded.                      */
+  int fused_pass;       /* 1: each inner pass pair of frpca_run (A^T (A Q) in Alg. 6,
+                           A (A^T Q) in Alg. 5) runs as one sweep: t_r = a_r Q is formed in
+                           registers and a_r^T t_r is added into the short-side panel with
+                           floating-point atomics, so the long-side panel is never stored.
+                           The order of the atomic adds varies, so results are not bitwise
+                           repeatable; not with center or panel_bf16. 0 (default): the two
+                           deterministic products of the merge-path plans.            */
 } frpca_opts;
 
 typedef struct {
@@ -151,6 +163,25 @@ int frpca_run(frpca_t h, int k, int p_passes, int s_oversample, uint64_t seed, f
  */
 int frpca_run_basic(frpca_t h, int k, int p_power, int s_oversample, uint64_t seed, int alg, float* U,
                     float* S, float* V);
+
+/*
+ * frpca_eigsvds - rank-k truncated SVD by eigSVDs (Alg. 3, Section 3.1): the k largest
+ * eigenpairs of B = A^T A (m >= n; A A^T when m < n, the smaller Gram matrix), S = their
+ * square roots, V the eigenvectors, U = A V diag(1/S). The eigenpairs come from a block
+ * subspace iteration on B with Rayleigh-Ritz steps, as eigs(B, k) would compute them: a
+ * block of l = k + s_oversample >= k columns starts from a Gaussian matrix (normal(seed,
+ * r*l + j) as in frpca_run) orthonormalised by CholeskyQR2; each step applies a Chebyshev
+ * filter of degree 8 that damps the spectrum below the block's smallest Ritz value,
+ * re-orthonormalises, and takes the Ritz pairs of Q^T B Q; it stops when every one of the k
+ * largest Ritz pairs has residual ||B w - theta w|| <= tol * theta_max (tol <= 0 selects
+ * 1e-6) or after max_iter Rayleigh-Ritz steps. B is applied as A^T (A P), never formed.
+ * Outputs, rank and sign conventions as frpca_run; *iters (host int, may be NULL) receives
+ * the number of Rayleigh-Ritz steps. The first call allocates two more short-side panels.
+ * frpca_backward does not apply (ESTATE afterwards). Errors: EINVAL (k < 1, s < 0,
+ * k+s > min(m,n), k+s > 128, max_iter < 1), ENOMEM, EHIP.
+ */
+int frpca_eigsvds(frpca_t h, int k, int s_oversample, uint64_t seed, double tol, int max_iter, float* U,
+                  float* S, float* V, int* iters);
 
 /*
  * frpca_backward - dL/d(values of A) from dL/dU, dL/dS, dL/dV of the handle's last frpca_run,
@@ -248,6 +279,13 @@ int frpca_orth(frpca_t h, int64_t rows, int l, const float* X, int ldx, float* Q
  * = U_R diag(sqrt(d)) W^T with d (device double[l]) ascending and W (device double[l*l],
  * row-major, column j paired with d[j]) orthonormal; l <= 128. */
 int frpca_jacobi_svd(frpca_t h, int l, const double* R, double* W, double* d);
+
+/* One inner pass pair (Section 3.3): out = A^T (A in) when m >= n, A (A^T in) when m < n,
+ * for short-side panels in/out (device float, min(m,n) x ld, ld = l rounded up to 32,
+ * l <= 128; pad columns of in must be 0, those of out are 0). fused = 0: the two merge-path
+ * products through the handle's long-side workspace (deterministic); fused = 1: the one-sweep
+ * form of opts.fused_pass (atomic adds). */
+int frpca_pass(frpca_t h, int l, const float* in, float* out, int fused);
 
 /* LU basis (Lemma 3, eq. 8): Q = P^T L of P X = L U with pivots chosen by tournament
  * pivoting (partial pivoting inside each node); pivot rows of Q form a unit lower-triangular

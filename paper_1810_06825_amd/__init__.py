@@ -33,9 +33,9 @@ class FrPCA:
     """
 
     def __init__(self, row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, shape,
-                 panel_bf16: bool = False, sign_fix: bool = True, rank_tol: float = 0.0,
+                 panel_bf16: int = 0, sign_fix: bool = True, rank_tol: float = 0.0,
                  timing: bool = False, max_workspace: int = 0, center: bool = False,
-                 gram_f32: bool = False):
+                 gram_f32: bool = False, fused_pass: bool = False):
         assert row_ptr.is_cuda and col.is_cuda and val.is_cuda
         assert row_ptr.dtype == torch.int64 and col.dtype == torch.int32 and val.dtype == torch.float32
         self.row_ptr = row_ptr.contiguous()
@@ -45,7 +45,7 @@ class FrPCA:
         self.nnz = int(self.col.numel())
         self.device = self.val.device
         opts = FrpcaOpts(int(panel_bf16), int(not sign_fix), float(rank_tol), int(timing), int(max_workspace),
-                         int(center), int(gram_f32))
+                         int(center), int(gram_f32), int(fused_pass))
         self.h = binding.frpca_create(self.m, self.n, self.nnz, self.row_ptr, self.col, self.val, opts,
                                       _stream())
         self.run_id = 0      # runs so far; frpca_backward refers to the last one
@@ -114,6 +114,17 @@ class FrPCA:
         binding.frpca_run_basic(self.h, k, power, s, seed, alg, U, S, V)
         self.run_id += 1
         return U, S, V
+
+    def eigsvds(self, k: int, s: int, seed: int, tol: float = 0.0, max_iter: int = 100):
+        """Rank-k truncated SVD by eigSVDs (Alg. 3): the k largest eigenpairs of A^T A by a
+        Chebyshev-filtered block subspace iteration (frpca_eigsvds). Returns (U, S, V, iters)."""
+        self._sync_stream()
+        U = torch.empty((self.m, k), dtype=torch.float32, device=self.device)
+        S = torch.empty((k,), dtype=torch.float32, device=self.device)
+        V = torch.empty((self.n, k), dtype=torch.float32, device=self.device)
+        it = binding.frpca_eigsvds(self.h, k, s, seed, tol, max_iter, U, S, V)
+        self.run_id += 1
+        return U, S, V, it
 
     def _grads(self, k, dU, dS, dV):
         out = []

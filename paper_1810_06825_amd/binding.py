@@ -32,7 +32,7 @@ class FrpcaError(RuntimeError):
 class FrpcaOpts(ctypes.Structure):
     _fields_ = [("panel_bf16", c_int), ("no_sign_fix", c_int), ("rank_tol", c_double),
                 ("timing", c_int), ("max_workspace", c_size_t), ("center", c_int),
-                ("gram_f32", c_int)]
+                ("gram_f32", c_int), ("fused_pass", c_int)]
 
 
 class FrpcaInfo(ctypes.Structure):
@@ -50,6 +50,8 @@ _SIGNATURES = {
     "frpca_set_stream": (c_int, [c_void_p, c_void_p]),
     "frpca_run": (c_int, [c_void_p, c_int, c_int, c_int, c_uint64, c_void_p, c_void_p, c_void_p]),
     "frpca_run_basic": (c_int, [c_void_p, c_int, c_int, c_int, c_uint64, c_int, c_void_p, c_void_p, c_void_p]),
+    "frpca_eigsvds": (c_int, [c_void_p, c_int, c_int, c_uint64, c_double, c_int, c_void_p, c_void_p, c_void_p,
+                              POINTER(c_int)]),
     "frpca_backward": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "frpca_adjoint": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                               c_void_p]),
@@ -66,6 +68,7 @@ _SIGNATURES = {
     "frpca_lu": (c_int, [c_void_p, c_int64, c_int, c_void_p, c_int, c_void_p, c_int, c_double, POINTER(c_int)]),
     "frpca_orth": (c_int, [c_void_p, c_int64, c_int, c_void_p, c_int, c_void_p, c_int, c_void_p, POINTER(c_int)]),
     "frpca_jacobi_svd": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p]),
+    "frpca_pass": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_int]),
     "frpca_tsmm": (c_int, [c_void_p, c_int64, c_int, c_int, c_void_p, c_int, c_void_p, c_void_p, c_int]),
     "frpca_sddmm": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "frpca_export_csc": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
@@ -133,6 +136,13 @@ def frpca_run_basic(h, k, p_power, s_oversample, seed, alg, U, S, V):
     _check(load().frpca_run_basic(h, k, p_power, s_oversample, seed, alg, _ptr(U), _ptr(S), _ptr(V)), h)
 
 
+def frpca_eigsvds(h, k, s_oversample, seed, tol, max_iter, U, S, V) -> int:
+    it = c_int(0)
+    _check(load().frpca_eigsvds(h, k, s_oversample, seed, tol, max_iter, _ptr(U), _ptr(S), _ptr(V), ctypes.byref(it)),
+           h)
+    return it.value
+
+
 def frpca_backward(h, dU, dS, dV, dval):
     _check(load().frpca_backward(h, _ptr(dU), _ptr(dS), _ptr(dV), _ptr(dval)), h)
 
@@ -198,6 +208,10 @@ def frpca_orth(h, rows, l, X, ldx, Q, ldq, R=None) -> int:
 
 def frpca_jacobi_svd(h, l, R, W, d):
     _check(load().frpca_jacobi_svd(h, l, _ptr(R), _ptr(W), _ptr(d)), h)
+
+
+def frpca_pass(h, l, inp, out, fused):
+    _check(load().frpca_pass(h, l, _ptr(inp), _ptr(out), fused), h)
 
 
 def frpca_tsmm(h, rows, kdim, c, X, ldx, B, out, ldo):

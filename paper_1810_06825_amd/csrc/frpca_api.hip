@@ -26,6 +26,10 @@ constexpr double kDefaultRankTol = 1e-5;
 // Cholesky pivot guard of orth() in the basic algorithms: a column whose residual norm falls
 // below about 3e-7 of its own norm is numerically dependent on the earlier ones.
 constexpr double kCholTol = 1e-13;
+// degree of the Chebyshev filter between Rayleigh-Ritz steps of eigSVDs
+constexpr int kChebDegree = 8;
+// residual level below which FP32 panels cannot resolve a Ritz pair, relative to theta_max
+constexpr double kResFloor = 2e-7;
 
 size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
@@ -119,6 +123,12 @@ struct frpca_ctx {
   size_t ws2_bytes = 0;
   int ws2_lp = 0;
   float* Z2 = nullptr;
+  // two more short-side panels, the residual partials and the residuals of eigSVDs
+  void* ws3 = nullptr;
+  size_t ws3_bytes = 0;
+  int ws3_lp = 0;
+  float *S3 = nullptr, *S4 = nullptr;
+  double *res_tmp = nullptr, *res = nullptr;
   float* Skeep = nullptr;  // singular values of the last run (library copy)
   int *order = nullptr, *ndrop = nullptr;
   double* eig_tmp = nullptr;
@@ -162,6 +172,7 @@ struct frpca_ctx {
     if (ws) (void)hipFree(ws);
     if (bws) (void)hipFree(bws);
     if (ws2) (void)hipFree(ws2);
+    if (ws3) (void)hipFree(ws3);
   }
 
   void* alloc_owned(size_t bytes) {
@@ -222,14 +233,14 @@ struct frpca_ctx {
   }
 
   void build_plan(MergePlan& p, const int32_t* ptr, const int32_t* idx, const float* v, int64_t nseg,
-                  bool sweep = false, int64_t plan_nnz = -1) {
+                  bool sweep = false, int64_t plan_nnz = -1, int64_t sweep_ipw = kSweepItemsPerWave) {
     p.ptr = ptr;
     p.idx = idx;
     p.val = v;
     p.nseg = nseg;
     p.nnz = plan_nnz >= 0 ? plan_nnz : nnz;
     p.sweep = sweep ? 1 : 0;
-    p.ipw = sweep ? kSweepItemsPerWave : merge_items_per_wave(nseg, p.nnz);
+    p.ipw = sweep ? sweep_ipw : merge_items_per_wave(nseg, p.nnz);
     p.nwaves = std::max<int64_t>(1, (nseg + p.nnz + p.ipw - 1) / p.ipw);
     p.part_seg = static_cast<int32_t*>(alloc_owned((p.nwaves + 1) * sizeof(int32_t)));
     p.part_e = static_cast<int32_t*>(alloc_owned((p.nwaves + 1) * sizeof(int32_t)));
@@ -267,7 +278,7 @@ struct frpca_ctx {
       X = a.take<float>((size_t)Ns * lp);
       Qb = bf16 ? a.take<uint16_t>((size_t)Ns * lp) : nullptr;
       Z = a.take<float>((size_t)Nl * lp);
-      Y = bf16 ? nullptr : Z;
+      Y = Z;  // FP32 long-side panel of the inner passes (those not stored in BF16)
       Yb = bf16 ? a.take<uint16_t>((size_t)Nl * lp) : nullptr;
       gram_part = a.take<double>(gram_partial_bytes(lp) / sizeof(double));
       G = a.take<double>(kMaxL * kMaxL);
@@ -325,6 +336,37 @@ struct frpca_ctx {
     ws2_bytes = need;
     ws2_lp = lp;
     Z2 = static_cast<float*>(ws2);
+  }
+
+  void ensure_short2(int lp) {
+    if (ws3 && ws3_lp >= lp) return;
+    if (ws3) {
+      FRPCA_HIP(hipStreamSynchronize(stream));
+      FRPCA_HIP(hipFree(ws3));
+      ws3 = nullptr;
+      ws3_bytes = 0;
+    }
+    auto plan = [&](Arena& a) {
+      S3 = a.take<float>((size_t)short_rows() * lp);
+      S4 = a.take<float>((size_t)short_rows() * lp);
+      res_tmp = a.take<double>(resid_temp_bytes(short_rows()) / sizeof(double));
+      res = a.take<double>(kMaxL);
+    };
+    Arena probe;
+    plan(probe);
+    const size_t need = probe.used;
+    if (opts.max_workspace && need + ws_bytes + ws2_bytes + setup_bytes > opts.max_workspace)
+      throw Error{FRPCA_ENOMEM, "eigSVDs panels of " + std::to_string(need) + " bytes exceed opts.max_workspace"};
+    if (hipMalloc(&ws3, need) != hipSuccess) {
+      (void)hipGetLastError();
+      ws3 = nullptr;
+      throw Error{FRPCA_ENOMEM, "eigSVDs panel allocation of " + std::to_string(need) + " bytes failed"};
+    }
+    Arena real;
+    real.base = static_cast<char*>(ws3);
+    plan(real);
+    ws3_bytes = need;
+    ws3_lp = lp;
   }
 
   // orth() of the basic algorithms on a panel (rows x l, ld lp) in place, through tmp:
@@ -498,7 +540,12 @@ int frpca_create(frpca_t* out, int64_t m, int64_t n, int64_t nnz, const int64_t*
           FRPCA_HIP(hipStreamSynchronize(st));
           h->bptr_tail = static_cast<int32_t*>(h->alloc_owned((n - hh + 1) * sizeof(int32_t)));
           launch_rebase(h->bptr + nhs, n - hh + 1, nnz_hot, h->bptr_tail, st);
-          h->build_plan(h->bhotp, h->bptr, h->brow, h->bval, nhs, true, nnz_hot);
+          // sweep partitions sized so the band of items in flight (the resident waves, 512 per
+          // XCD, each on one partition) covers about two row blocks per XCD, whose rows of Y
+          // (2 MB each at l = 128) then stay in that XCD's 4 MB L2
+          const int64_t sweep_ipw =
+              std::max<int64_t>(kSweepMinIpw, std::min<int64_t>(kSweepItemsPerWave, nnz_hot / nblk / 256));
+          h->build_plan(h->bhotp, h->bptr, h->brow, h->bval, nhs, true, nnz_hot, sweep_ipw);
           h->build_plan(h->btailp, h->bptr_tail, h->brow + nnz_hot, h->bval + nnz_hot, n - hh, false,
                         nnz - nnz_hot);
           h->btailp.out_row = h->btailcol;  // tail segment i is column btailcol[i] of the result
@@ -563,9 +610,19 @@ int frpca_run(frpca_t h, int k, int p_passes, int s_oversample, uint64_t seed, f
     FRPCA_CHECK(p_passes >= 2, FRPCA_EINVAL, "the pass parameter q must be >= 2 (Alg. 5/6)");
     FRPCA_CHECK(U && S && V, FRPCA_EINVAL, "NULL output");
     const int LP = panel_ld(l);
-    const int bf = h->opts.panel_bf16 ? 1 : 0;
+    const int bfmode = h->opts.panel_bf16;
+    FRPCA_CHECK(bfmode >= 0 && bfmode <= 3, FRPCA_EINVAL, "opts.panel_bf16 must be 0, 1, 2 or 3");
     h->saved_k = 0;
-    h->ensure_workspace(LP, bf);
+    h->ensure_workspace(LP, bfmode ? 1 : 0);
+    // which inner pass pairs store their panels in BF16: all of them (modes 1 and 3) or all but
+    // the last one, whose basis feeds the final Rayleigh-Ritz step (mode 2); mode 3 stores only
+    // the basis read by the forward product in BF16 and keeps the long-side panel in FP32
+    const int last = (p_passes - 1) / 2;
+    auto bf_pair = [&](int i) { return bfmode == 1 || bfmode == 3 || (bfmode == 2 && i < last); };
+    const bool bf_long = bfmode != 3;  // the long-side panel follows the pass pair's choice
+    const bool fused = h->opts.fused_pass != 0;
+    FRPCA_CHECK(!fused || (!h->opts.center && !bfmode), FRPCA_EINVAL,
+                "opts.fused_pass does not combine with center or panel_bf16");
     hipStream_t st = h->stream;
     const bool a6 = m >= n;
     const MergePlan& Fp = a6 ? h->csr : h->csc;  // short side -> long side
@@ -600,14 +657,16 @@ int frpca_run(frpca_t h, int k, int p_passes, int s_oversample, uint64_t seed, f
     };
     // forward product (short side -> long side): A Q for Alg. 6, A^T Q for Alg. 5
     auto forward_corr = [&](const void* in, bool in_b) { return a6 ? corr_a(in, in_b) : corr_at(in, in_b); };
-    auto forward_inner = [&] {
-      if (bf) spmm(Fp, fwd_cls, h->Qb, true, nullptr, h->Yb, forward_corr(h->Qb, true));
+    auto forward_inner = [&](bool bf) {
+      if (bf && bf_long) spmm(Fp, fwd_cls, h->Qb, true, nullptr, h->Yb, forward_corr(h->Qb, true));
+      else if (bf) spmm(Fp, fwd_cls, h->Qb, true, h->Y, nullptr, forward_corr(h->Qb, true));
       else spmm(Fp, fwd_cls, h->Q, false, h->Y, nullptr, forward_corr(h->Q, false));
     };
     // back product (long side -> short side). For Alg. 6 the panel Y = (A - 1 mu^T) Q of a
     // centred forward product has 1^T Y = (1^T A - m mu^T) Q = 0 exactly, so the term is
     // skipped there (input_centred); the Gaussian start of even q has it.
-    auto back = [&](bool input_centred) {
+    auto back = [&](bool input_centred, bool bf_pass) {
+      const bool bf = bf_pass && bf_long;
       const void* in = bf ? static_cast<const void*>(h->Yb) : static_cast<const void*>(h->Y);
       SpmmCorr corr{};
       if (cen && !(a6 && input_centred)) corr = a6 ? corr_at(in, bf != 0) : corr_a(in, bf != 0);
@@ -620,16 +679,17 @@ int frpca_run(frpca_t h, int k, int p_passes, int s_oversample, uint64_t seed, f
         spmm(Bp, back_cls, in, bf != 0, h->X, nullptr, corr);
       }
     };
-    auto basis_from_B1 = [&] {
+    // the new basis also gets a BF16 copy when the next pass pair reads BF16 panels
+    auto basis_from_B1 = [&](bool next_bf) {
       frpca_ctx::Scope t(h, FRPCA_T_TSMM);
-      launch_tsmm(h->X, false, LP, Ns, l, h->B1, LP, l, LP, h->Q, LP, bf ? h->Qb : nullptr, LP, st);
+      launch_tsmm(h->X, false, LP, Ns, l, h->B1, LP, l, LP, h->Q, LP, next_bf ? h->Qb : nullptr, LP, st);
     };
-    auto orth_lu = [&] {
+    auto orth_lu = [&](bool next_bf) {
       {
         frpca_ctx::Scope t(h, FRPCA_T_LU);
         launch_lu_coeffs(h->X, LP, Ns, l, kInnerTol, h->B1, LP, h->lu_tmp, h->ndrop + 1, st);
       }
-      basis_from_B1();
+      basis_from_B1(next_bf);
     };
     auto gram_eig = [&](const float* P, int64_t rows) {
       {
@@ -639,31 +699,37 @@ int frpca_run(frpca_t h, int k, int p_passes, int s_oversample, uint64_t seed, f
       frpca_ctx::Scope t(h, FRPCA_T_EIG);
       launch_eig(h->G, l, l, h->d, h->W, h->eig_tmp, st);
     };
-    auto orth_eig = [&] {
+    auto orth_eig = [&](bool next_bf) {
       gram_eig(h->X, Ns);
       launch_eigsvd_coeffs(h->d, h->W, l, LP, kInnerTol, h->B1, nullptr, st);
-      basis_from_B1();
+      basis_from_B1(next_bf);
     };
 
-    // start of the pass schedule
+    // start of the pass schedule (the start counts as pass pair 0 for the BF16 schedule)
     if (p_passes % 2 == 0) {
+      const bool bf0 = bf_pair(0) && bf_long;
       {
         frpca_ctx::Scope t(h, FRPCA_T_GAUSS);  // long-side Gaussian (the transposed randn(k+s, .))
-        launch_gaussian(seed, Nl, l, LP, bf ? nullptr : h->Y, bf ? h->Yb : nullptr, st);
+        launch_gaussian(seed, Nl, l, LP, bf0 ? nullptr : h->Y, bf0 ? h->Yb : nullptr, st);
       }
-      back(false);
-      if (p_passes == 2) orth_eig();
-      else orth_lu();
+      back(false, bf0);
+      if (p_passes == 2) orth_eig(false);
+      else orth_lu(bf_pair(1));
     } else {
       frpca_ctx::Scope t(h, FRPCA_T_GAUSS);
-      launch_gaussian(seed, Ns, l, LP, h->Q, bf ? h->Qb : nullptr, st);
+      launch_gaussian(seed, Ns, l, LP, h->Q, last >= 1 && bf_pair(1) ? h->Qb : nullptr, st);
     }
-    const int last = (p_passes - 1) / 2;
     for (int i = 1; i <= last; ++i) {
-      forward_inner();
-      back(true);
-      if (i == last) orth_eig();
-      else orth_lu();
+      const bool bf = bf_pair(i);
+      if (fused) {
+        frpca_ctx::Scope t(h, FRPCA_T_SPMM_F);
+        launch_fused_pass(Fp.ptr, Fp.idx, Fp.val, Fp.nseg, h->Q, LP, LP, h->X, LP, Ns, st);
+      } else {
+        forward_inner(bf);
+        back(true, bf);
+      }
+      if (i == last) orth_eig(false);
+      else orth_lu(bf_pair(i + 1));
     }
     // final pass and Rayleigh-Ritz: eigSVD of the long-side panel Z
     spmm(Fp, fwd_cls, h->Q, false, h->Z, nullptr, forward_corr(h->Q, false));
@@ -802,6 +868,179 @@ int frpca_run_basic(frpca_t h, int k, int p_power, int s_oversample, uint64_t se
     h->info.k = k;
     h->info.s = s_oversample;
     h->info.passes = 2 * p_power + 2;
+  });
+}
+
+int frpca_eigsvds(frpca_t h, int k, int s_oversample, uint64_t seed, double tol, int max_iter, float* U, float* S,
+                  float* V, int* iters) {
+  if (!h) return fail(nullptr, Error{FRPCA_EINVAL, "NULL handle"});
+  return guarded(h, [&] {
+    const int64_t m = h->m, n = h->n;
+    FRPCA_CHECK(k >= 1 && s_oversample >= 0, FRPCA_EINVAL, "need k >= 1 and s >= 0");
+    const int l = k + s_oversample;
+    FRPCA_CHECK(l <= std::min(m, n), FRPCA_EINVAL, "need k + s <= min(m, n)");
+    FRPCA_CHECK(l <= kMaxL, FRPCA_EINVAL, "need k + s <= 128");
+    FRPCA_CHECK(max_iter >= 1, FRPCA_EINVAL, "max_iter must be >= 1");
+    FRPCA_CHECK(!h->opts.center, FRPCA_EINVAL, "the centred products apply to frpca_run only");
+    FRPCA_CHECK(U && S && V, FRPCA_EINVAL, "NULL output");
+    if (tol <= 0.0) tol = 1e-6;
+    const int LP = panel_ld(l);
+    h->saved_k = 0;
+    h->ensure_workspace(LP, h->opts.panel_bf16 ? 1 : 0);
+    h->ensure_short2(LP);
+    hipStream_t st = h->stream;
+    const bool a6 = m >= n;
+    const MergePlan& Fp = a6 ? h->csr : h->csc;  // short side -> long side
+    const MergePlan& Bp = a6 ? h->csc : h->csr;  // long side -> short side
+    const int64_t Ns = h->short_rows(), Nl = h->long_rows();
+    auto spmm = [&](const MergePlan& p, int cls, const float* in, float* out) {
+      {
+        frpca_ctx::Scope t(h, cls);
+        launch_spmm_main(p, LP, in, false, LP, out, nullptr, LP, st);
+      }
+      frpca_ctx::Scope t(h, FRPCA_T_SPMM_FIX);
+      launch_spmm_fixup(p, LP, out, nullptr, LP, st);
+    };
+    auto forward = [&](const float* in, float* out) { spmm(Fp, FRPCA_T_SPMM_F, in, out); };
+    auto back = [&](const float* in, float* out) {
+      if (a6 && h->has_bcsc) {
+        spmm(h->bhotp, FRPCA_T_SPMM_B, in, h->bpart);
+        spmm(h->btailp, FRPCA_T_SPMM_TAIL, in, out);
+        frpca_ctx::Scope t(h, FRPCA_T_SPMM_COMB);
+        launch_bcsc_combine(h->bpart, LP, h->bhotcol, h->bhot, h->bnblk, LP, out, nullptr, LP, st);
+      } else {
+        spmm(Bp, FRPCA_T_SPMM_B, in, out);
+      }
+    };
+    // B P = A^T (A P) for a short-side panel P (m >= n; A A^T for m < n): B is never formed
+    auto apply_B = [&](const float* P, float* out) {
+      forward(P, h->Z);
+      back(h->Z, out);
+    };
+    // four short-side panels change roles: the basis, B times it, and two filter iterates
+    float* buf[4] = {h->Q, h->X, h->S3, h->S4};
+    float* Qc = buf[0];
+    {
+      frpca_ctx::Scope t(h, FRPCA_T_GAUSS);  // starting block: a Gaussian n x l matrix
+      launch_gaussian(seed, Ns, l, LP, Qc, nullptr, st);
+    }
+    h->orth_cqr2(Qc, buf[1], Ns, l, LP, nullptr, st);
+    std::vector<double> r2(l), theta(l), hist;
+    int it = 0;
+    for (;;) {
+      ++it;
+      // Rayleigh-Ritz on range(Qc): H = Qc^T B Qc, (theta, W) = eig(H), Ritz vectors Qc W
+      float* BQ = Qc == buf[1] ? buf[0] : buf[1];
+      apply_B(Qc, BQ);
+      {
+        frpca_ctx::Scope t(h, FRPCA_T_GRAM);
+        launch_gram(Qc, false, LP, BQ, LP, Ns, l, h->gram_part, h->G, l, st, false);
+        launch_symmetrize(h->G, l, st);
+      }
+      {
+        frpca_ctx::Scope t(h, FRPCA_T_EIG);
+        launch_eig(h->G, l, l, h->d, h->W, h->eig_tmp, st);
+      }
+      if (it == max_iter) break;
+      // residuals of the Ritz pairs: || B (Qc W) - theta (Qc W) || with B (Qc W) = (B Qc) W
+      float* R1 = nullptr;
+      float* R2 = nullptr;
+      for (float* b : buf)
+        if (b != Qc && b != BQ) (R1 ? R2 : R1) = b;
+      {
+        frpca_ctx::Scope t(h, FRPCA_T_TSMM);
+        launch_tsmm(Qc, false, LP, Ns, l, h->W, l, l, LP, R1, LP, nullptr, 0, st);
+        launch_tsmm(BQ, false, LP, Ns, l, h->W, l, l, LP, R2, LP, nullptr, 0, st);
+      }
+      launch_resid_norms(R1, R2, LP, Ns, l, h->d, h->res_tmp, h->res, st);
+      check_launch();
+      FRPCA_HIP(hipMemcpyAsync(r2.data(), h->res, l * sizeof(double), hipMemcpyDeviceToHost, st));
+      FRPCA_HIP(hipMemcpyAsync(theta.data(), h->d, l * sizeof(double), hipMemcpyDeviceToHost, st));
+      FRPCA_HIP(hipStreamSynchronize(st));
+      // converged when each of the k largest Ritz pairs has ||B w - theta w|| <= tol theta
+      // (relative to its own eigenvalue), or <= kResFloor theta_max, the level at which FP32
+      // panels stop resolving it; a Ritz value of 0 (a direction the basis lost) never counts
+      const double tmax = std::max(theta[l - 1], 0.0);
+      if (!(tmax > 0.0)) break;
+      bool conv = true;
+      double worst = 0.0;
+      for (int j = l - k; j < l; ++j) {
+        const double rj = std::sqrt(std::max(r2[j], 0.0));
+        conv = conv && theta[j] > 0.0 && rj <= std::max(tol * theta[j], kResFloor * tmax);
+        worst = std::max(worst, rj / std::max(theta[j], 1e-300 * tmax));
+      }
+      if (conv) break;
+      // stagnation (no 10% gain of the worst relative residual over three steps) ends it too
+      hist.push_back(worst);
+      if (hist.size() >= 4 && !(worst < 0.9 * hist[hist.size() - 4])) break;
+      // Chebyshev filter of degree kChebDegree on the Ritz vectors: damp [0, theta_min] (the
+      // unwanted part of the spectrum lies below the block's smallest Ritz value), normalised
+      // at theta_max (the scaled three-term recurrence of Zhou and Saad, 2007)
+      const double bcut = std::max(theta[0], 0.0);
+      const double e = 0.5 * bcut, c = 0.5 * bcut;
+      if (!(tmax > bcut * (1.0 + 1e-12)) || e <= 0.0) break;  // no spectral gap to exploit
+      // degree: the filter grows the largest Ritz value T_d(x_max) times more than the k-th
+      // largest; that ratio stays below 1e4 so no wanted direction sinks under FP32 rounding
+      // in the filtered block (degree 1 is a plain power step)
+      const double xmax = (tmax - c) / e, xk = (std::max(theta[l - k], 0.0) - c) / e;
+      int degree = 1;
+      {
+        double a0 = 1.0, a1 = xmax, b0 = 1.0, b1 = xk;  // T_0, T_1 at x_max and x_k
+        for (int dgr = 2; dgr <= kChebDegree; ++dgr) {
+          const double a2 = 2.0 * xmax * a1 - a0, b2 = 2.0 * xk * b1 - b0;
+          if (!(std::fabs(a2) <= 1e4 * std::fabs(b2))) break;
+          degree = dgr;
+          a0 = a1;
+          a1 = a2;
+          b0 = b1;
+          b1 = b2;
+        }
+      }
+      double sigma = e / (tmax - c);
+      const double tau = 2.0 / sigma;
+      float* Xprev = R1;  // Ritz vectors Qc W (the filter's start)
+      float* Ycur = R2;
+      float* BY = BQ;
+      apply_B(Xprev, BY);
+      launch_panel_comb(Ns, l, LP, (float)(sigma / e), BY, (float)(-c * sigma / e), Xprev, 0.f, nullptr, Ycur, st);
+      for (int deg = 2; deg <= degree; ++deg) {
+        const double sigma_new = 1.0 / (tau - sigma);
+        apply_B(Ycur, BY);
+        // Y_next = (2 sigma_new / e) (B Y - c Y) - sigma sigma_new X, written over X
+        launch_panel_comb(Ns, l, LP, (float)(2.0 * sigma_new / e), BY, (float)(-2.0 * sigma_new * c / e), Ycur,
+                          (float)(-sigma * sigma_new), Xprev, Xprev, st);
+        std::swap(Xprev, Ycur);
+        sigma = sigma_new;
+      }
+      Qc = Ycur;
+      h->orth_cqr2(Qc, BY, Ns, l, LP, nullptr, st);
+    }
+    // final step as in Alg. 5/6 with the converged basis: Z = (A Q), the eigenpairs of
+    // H = Q^T B Q = Z^T Z (already in d, W), U = Z W / sigma and V = Q W for the k largest
+    forward(Qc, h->Z);
+    launch_final_coeffs(h->d, h->W, l, k, LP, h->rank_tol, h->B1, h->B2, S, h->Skeep, h->ndrop, st);
+    float* out_long = a6 ? U : V;
+    float* out_short = a6 ? V : U;
+    {
+      frpca_ctx::Scope t(h, FRPCA_T_TSMM);
+      if (a6) launch_tsmm(Qc, false, LP, Ns, l, h->B2, LP, k, k, out_short, k, nullptr, 0, st);
+      else launch_tsmm(h->Z, false, LP, Nl, l, h->B1, LP, k, k, out_long, k, nullptr, 0, st);
+    }
+    if (!h->opts.no_sign_fix) {
+      frpca_ctx::Scope t(h, FRPCA_T_SIGN);
+      if (a6) launch_sign_fix(V, n, k, h->B1, h->B2, LP, l, h->sign_tmp, st);
+      else launch_sign_fix(V, n, k, h->B2, h->B1, LP, l, h->sign_tmp, st);
+    }
+    {
+      frpca_ctx::Scope t(h, FRPCA_T_TSMM);
+      if (a6) launch_tsmm(h->Z, false, LP, Nl, l, h->B1, LP, k, k, out_long, k, nullptr, 0, st);
+      else launch_tsmm(Qc, false, LP, Ns, l, h->B2, LP, k, k, out_short, k, nullptr, 0, st);
+    }
+    check_launch();
+    h->info.k = k;
+    h->info.s = s_oversample;
+    h->info.passes = 0;
+    if (iters) *iters = it;
   });
 }
 
@@ -945,7 +1184,7 @@ int frpca_get_info(frpca_t h, frpca_info* info) {
       FRPCA_HIP(hipStreamSynchronize(h->stream));
       h->info.rank_dropped = nd;
     }
-    h->info.workspace_bytes = h->setup_bytes + h->ws_bytes + h->bws_bytes + h->ws2_bytes;
+    h->info.workspace_bytes = h->setup_bytes + h->ws_bytes + h->bws_bytes + h->ws2_bytes + h->ws3_bytes;
     *info = h->info;
   });
 }
@@ -1086,6 +1325,29 @@ int frpca_jacobi_svd(frpca_t h, int l, const double* R, double* W, double* d) {
     launch_jacobi_svd(R, l, l * 2.220446049250313e-16, d, W, h->stream);
     check_launch();
     FRPCA_HIP(hipStreamSynchronize(h->stream));
+  });
+}
+
+int frpca_pass(frpca_t h, int l, const float* in, float* out, int fused) {
+  if (!h) return fail(nullptr, Error{FRPCA_EINVAL, "NULL handle"});
+  return guarded(h, [&] {
+    FRPCA_CHECK(l >= 1 && l <= kMaxL && l <= std::min(h->m, h->n) && in && out, FRPCA_EINVAL,
+                "bad pass arguments");
+    const int LP = panel_ld(l);
+    h->ensure_workspace(LP, h->opts.panel_bf16 ? 1 : 0);
+    hipStream_t st = h->stream;
+    const bool a6 = h->m >= h->n;
+    const MergePlan& Fp = a6 ? h->csr : h->csc;
+    const MergePlan& Bp = a6 ? h->csc : h->csr;
+    if (fused) {
+      launch_fused_pass(Fp.ptr, Fp.idx, Fp.val, Fp.nseg, in, LP, LP, out, LP, h->short_rows(), st);
+    } else {
+      launch_spmm(Fp, LP, in, false, LP, h->Z, nullptr, LP, st);
+      if (a6 && h->has_bcsc) h->bcsc_product(LP, h->Z, false, LP, h->bpart, out, nullptr, LP, st);
+      else launch_spmm(Bp, LP, h->Z, false, LP, out, nullptr, LP, st);
+    }
+    check_launch();
+    FRPCA_HIP(hipStreamSynchronize(st));
   });
 }
 

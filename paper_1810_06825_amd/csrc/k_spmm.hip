@@ -227,6 +227,9 @@ __global__ __launch_bounds__(256) void spmm_merge_kernel(SpmmArgs a) {
 #define FRPCA_SPMM_PAIRS 4
 #endif
 constexpr int kPairs = FRPCA_SPMM_PAIRS;  // pairs per batch; two batches in flight
+#ifndef FRPCA_SPMM_NT_STORE
+#define FRPCA_SPMM_NT_STORE 1
+#endif
 
 template <bool IN_BF16>
 __device__ __forceinline__ float4 load4(const void* base, size_t idx) {
@@ -289,7 +292,17 @@ __device__ __forceinline__ void spmm_partition4(const SpmmArgs& a, int64_t w, in
           t.w -= sc * cv.w;
         }
         const size_t o = (size_t)orow * a.ld_out + col;
+#if FRPCA_SPMM_NT_STORE
+        // streaming stores: output rows are not read again by this launch, so they should not
+        // displace gathered panel rows from L2
+        typedef float v4f __attribute__((ext_vector_type(4)));
+        if (a.out_f32) {
+          const v4f tv = {t.x, t.y, t.z, t.w};
+          __builtin_nontemporal_store(tv, reinterpret_cast<v4f*>(a.out_f32 + o));
+        }
+#else
         if (a.out_f32) *reinterpret_cast<float4*>(a.out_f32 + o) = t;
+#endif
         if (a.out_bf16) {
           uint2 b;
           b.x = (uint32_t)f32_to_bf16(t.x) | ((uint32_t)f32_to_bf16(t.y) << 16);

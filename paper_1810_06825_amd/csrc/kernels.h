@@ -94,7 +94,11 @@ int64_t merge_items_per_wave(int64_t nseg, int64_t nnz);
 #ifndef FRPCA_SWEEP_IPW
 #define FRPCA_SWEEP_IPW 384
 #endif
-constexpr int64_t kSweepItemsPerWave = FRPCA_SWEEP_IPW;  // partition size of sweep-mode plans
+constexpr int64_t kSweepItemsPerWave = FRPCA_SWEEP_IPW;  // largest partition of sweep-mode plans
+#ifndef FRPCA_SWEEP_MIN_IPW
+#define FRPCA_SWEEP_MIN_IPW 96
+#endif
+constexpr int64_t kSweepMinIpw = FRPCA_SWEEP_MIN_IPW;   // smallest partition of sweep-mode plans
 void launch_merge_partition(MergePlan& p, hipStream_t st);
 void launch_merge_fixplan(MergePlan& p, hipStream_t st);
 // out[seg, 0:lp) = sum_{e in seg} val[e] * in[idx[e], 0:lp)  (lp even, <= 128):
@@ -159,6 +163,25 @@ void launch_small_matmul(const double* A, const double* B, int l, double* C, hip
 // One-sided Jacobi SVD of R (l x l, ld l): d = sigma^2 ascending, W (l x l row-major) the
 // right singular vectors of R paired with d (the layout of launch_eig).
 void launch_jacobi_svd(const double* R, int l, double tol, double* d, double* W, hipStream_t st);
+
+// ---------------------------------------------------------------- eigSVDs (k_cheb.hip)
+// out = a X + b Y + c Z elementwise over a rows x ld panel (columns >= cols set to 0);
+// Z may be null, out may alias Z.
+void launch_panel_comb(int64_t rows, int cols, int ld, float a, const float* X, float b, const float* Y, float c,
+                       const float* Z, float* out, hipStream_t st);
+// out[j] = || Z[:, j] - theta_j Q[:, j] ||^2 for j < l (FP64, fixed-order reduction).
+size_t resid_temp_bytes(int64_t rows);
+// G = (G + G^T) / 2 (l x l, ld l) in place.
+void launch_symmetrize(double* G, int l, hipStream_t st);
+void launch_resid_norms(const float* Q, const float* Z, int ld, int64_t rows, int l, const double* theta,
+                        double* temp, double* out, hipStream_t st);
+
+// ---------------------------------------------------------------- fused pass pair (k_fused.hip)
+// X (xrows x ldx, zeroed first) = S^T (S Q) for the segment matrix S = (ptr, idx, val) with
+// nseg rows: t_r = s_r Q in registers, then atomic adds of s_r^T t_r into X (not bitwise
+// repeatable). Q rows and X rows 16-byte aligned, lp a multiple of 4.
+void launch_fused_pass(const int32_t* ptr, const int32_t* idx, const float* val, int64_t nseg, const float* Q,
+                       int ldq, int lp, float* X, int ldx, int64_t xrows, hipStream_t st);
 
 // ---------------------------------------------------------------- adjoint
 // From J = U^T dU, K = V^T dV (k x k, FP64, ld k) and S, dS: coefficient matrices
