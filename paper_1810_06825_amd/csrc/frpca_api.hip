@@ -973,44 +973,48 @@ int frpca_eigsvds(frpca_t h, int k, int s_oversample, uint64_t seed, double tol,
       // stagnation (no 10% gain of the worst relative residual over three steps) ends it too
       hist.push_back(worst);
       if (hist.size() >= 4 && !(worst < 0.9 * hist[hist.size() - 4])) break;
-      // Chebyshev filter of degree kChebDegree on the Ritz vectors: damp [0, theta_min] (the
-      // unwanted part of the spectrum lies below the block's smallest Ritz value), normalised
-      // at theta_max (the scaled three-term recurrence of Zhou and Saad, 2007)
-      const double bcut = std::max(theta[0], 0.0);
-      const double e = 0.5 * bcut, c = 0.5 * bcut;
-      if (!(tmax > bcut * (1.0 + 1e-12)) || e <= 0.0) break;  // no spectral gap to exploit
-      // degree: the filter grows the largest Ritz value T_d(x_max) times more than the k-th
-      // largest; that ratio stays below 1e4 so no wanted direction sinks under FP32 rounding
-      // in the filtered block (degree 1 is a plain power step)
-      const double xmax = (tmax - c) / e, xk = (std::max(theta[l - k], 0.0) - c) / e;
-      int degree = 1;
-      {
-        double a0 = 1.0, a1 = xmax, b0 = 1.0, b1 = xk;  // T_0, T_1 at x_max and x_k
-        for (int dgr = 2; dgr <= kChebDegree; ++dgr) {
-          const double a2 = 2.0 * xmax * a1 - a0, b2 = 2.0 * xk * b1 - b0;
-          if (!(std::fabs(a2) <= 1e4 * std::fabs(b2))) break;
-          degree = dgr;
-          a0 = a1;
-          a1 = a2;
-          b0 = b1;
-          b1 = b2;
-        }
-      }
-      double sigma = e / (tmax - c);
-      const double tau = 2.0 / sigma;
+      // Chebyshev filter on the Ritz vectors: damp [0, theta_min] (the unwanted part of the
+      // spectrum lies below the block's smallest Ritz value), normalised at theta_max (the scaled
+      // three-term recurrence of Zhou and Saad, 2007). Its degree (at most kChebDegree) keeps
+      // the growth of the largest Ritz value over the block's smallest, T_d(x_max), and over the
+      // k-th largest, T_d(x_max) / T_d(x_k), below 1e5 and 1e4, so no direction of the block
+      // sinks under FP32 rounding before the next orthonormalisation. Without a usable interval
+      // (theta_min <= 0 after a dropped direction, or no gap) the step is a plain power step.
       float* Xprev = R1;  // Ritz vectors Qc W (the filter's start)
       float* Ycur = R2;
       float* BY = BQ;
-      apply_B(Xprev, BY);
-      launch_panel_comb(Ns, l, LP, (float)(sigma / e), BY, (float)(-c * sigma / e), Xprev, 0.f, nullptr, Ycur, st);
-      for (int deg = 2; deg <= degree; ++deg) {
-        const double sigma_new = 1.0 / (tau - sigma);
-        apply_B(Ycur, BY);
-        // Y_next = (2 sigma_new / e) (B Y - c Y) - sigma sigma_new X, written over X
-        launch_panel_comb(Ns, l, LP, (float)(2.0 * sigma_new / e), BY, (float)(-2.0 * sigma_new * c / e), Ycur,
-                          (float)(-sigma * sigma_new), Xprev, Xprev, st);
-        std::swap(Xprev, Ycur);
-        sigma = sigma_new;
+      const double bcut = theta[0];
+      if (!(bcut > 0.0) || !(tmax > bcut * (1.0 + 1e-12))) {
+        apply_B(Xprev, Ycur);
+      } else {
+        const double e = 0.5 * bcut, c = 0.5 * bcut;
+        const double xmax = (tmax - c) / e, xk = (std::max(theta[l - k], 0.0) - c) / e;
+        int degree = 1;
+        {
+          double a0 = 1.0, a1 = xmax, b0 = 1.0, b1 = xk;  // T_0, T_1 at x_max and x_k
+          for (int dgr = 2; dgr <= kChebDegree; ++dgr) {
+            const double a2 = 2.0 * xmax * a1 - a0, b2 = 2.0 * xk * b1 - b0;
+            if (!(std::fabs(a2) <= 1e5) || !(std::fabs(a2) <= 1e4 * std::fabs(b2))) break;
+            degree = dgr;
+            a0 = a1;
+            a1 = a2;
+            b0 = b1;
+            b1 = b2;
+          }
+        }
+        double sigma = e / (tmax - c);
+        const double tau = 2.0 / sigma;
+        apply_B(Xprev, BY);
+        launch_panel_comb(Ns, l, LP, (float)(sigma / e), BY, (float)(-c * sigma / e), Xprev, 0.f, nullptr, Ycur, st);
+        for (int deg = 2; deg <= degree; ++deg) {
+          const double sigma_new = 1.0 / (tau - sigma);
+          apply_B(Ycur, BY);
+          // Y_next = (2 sigma_new / e) (B Y - c Y) - sigma sigma_new X, written over X
+          launch_panel_comb(Ns, l, LP, (float)(2.0 * sigma_new / e), BY, (float)(-2.0 * sigma_new * c / e), Ycur,
+                            (float)(-sigma * sigma_new), Xprev, Xprev, st);
+          std::swap(Xprev, Ycur);
+          sigma = sigma_new;
+        }
       }
       Qc = Ycur;
       h->orth_cqr2(Qc, BY, Ns, l, LP, nullptr, st);

@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 from gpu_util import ANG_TOL, SIG_TOL, compare_triplets, np64, say
-from synth import planted_blocks, zipf_lognormal, zipf_normal
+from synth import aminer_tfidf, planted_blocks, zipf_lognormal, zipf_normal
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -44,6 +44,15 @@ def test_wide_alg5_orientation():
     A = zipf_normal(m=2_500, n=30_000, t=20)
     r, it, _ = _check(A, 16, 10)
     assert r["ok"], r
+
+
+def test_flat_tfidf_spectrum():
+    """A few nonzeros per row with tf-idf values (the shape of the paper's Matrix 7): a flat
+    spectrum, where the filter stays at low degree and the iteration needs more steps."""
+    A = aminer_tfidf(m=200_000, n=8_000, t=4, seed=1008)
+    r, it, _ = _check(A, 50, 28)
+    assert r["ok"], r
+    assert it > 2
 
 
 def test_planted_closed_form():
