@@ -258,7 +258,8 @@ def headline(args, A, k, q, s, torch, np):
 
 
 def variants(A, k, q, s, steps, torch, np, S_ref):
-    """BF16 panels (every inner pass pair, or all but the last one), the FP32-MFMA Gram, the
+    """BF16 panels (every inner pass pair, all but the last one, or the long-side panel of all
+    but the last one), the FP32-MFMA Gram, the
     one-sweep pass pairs with atomic adds and the centred run on the headline matrix: time and
     singular-value difference against the default FP32 path."""
     from paper_1810_06825_amd import FrPCA
@@ -267,8 +268,8 @@ def variants(A, k, q, s, steps, torch, np, S_ref):
     Sf = S_ref.double().cpu().numpy()
     n = max(3, steps // 2)
     for name, kw in (("bf16_panel", {"panel_bf16": 1}), ("bf16_mixed", {"panel_bf16": 2}),
-                     ("gram_f32", {"gram_f32": True}), ("fused_pass", {"fused_pass": True}),
-                     ("centered", {"center": True})):
+                     ("bf16_long", {"panel_bf16": 4}), ("gram_f32", {"gram_f32": True}),
+                     ("fused_pass", {"fused_pass": True}), ("centered", {"center": True})):
         m2 = FrPCA.from_csr(A, device="cuda:0", **kw)
         t, (_, S2, _) = timed_runs(m2, k, q, s, n, 1, torch)
         m2.close()
@@ -312,7 +313,7 @@ def secondary_zipf(args, torch, np):
     # the precision and fusion variants on this matrix: time and sigma difference against FP32
     rec["variants"] = {}
     for name, vkw in (("bf16_panel", {"panel_bf16": 1}), ("bf16_mixed", {"panel_bf16": 2}),
-                      ("fused_pass", {"fused_pass": True})):
+                      ("bf16_long", {"panel_bf16": 4}), ("fused_pass", {"fused_pass": True})):
         mv = FrPCA.from_csr(A, device="cuda:0", **vkw)
         t, (_, Sv, _) = timed_runs(mv, k, q, s, max(3, args.steps // 2), 1, torch)
         mv.close()

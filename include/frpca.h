@@ -62,6 +62,7 @@ typedef struct {
                            so a BF16 rounding only perturbs the starting subspace of a pass
                            pair that follows. 3: only the basis read by the inner forward
                            products is stored in BF16 (the long-side panel stays FP32).
+                           4: as 2 for the long-side panel only (the basis stays FP32).
                            0 (default): FP32 panels.                                   */
   int no_sign_fix;      /* 0 (default): flip each (u_i, v_i) so that the largest-|.| entry
                            of v_i is positive (ties: lowest index). 1: leave signs.      */

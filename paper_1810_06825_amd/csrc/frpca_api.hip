@@ -611,15 +611,17 @@ int frpca_run(frpca_t h, int k, int p_passes, int s_oversample, uint64_t seed, f
     FRPCA_CHECK(U && S && V, FRPCA_EINVAL, "NULL output");
     const int LP = panel_ld(l);
     const int bfmode = h->opts.panel_bf16;
-    FRPCA_CHECK(bfmode >= 0 && bfmode <= 3, FRPCA_EINVAL, "opts.panel_bf16 must be 0, 1, 2 or 3");
+    FRPCA_CHECK(bfmode >= 0 && bfmode <= 4, FRPCA_EINVAL, "opts.panel_bf16 must be 0 .. 4");
     h->saved_k = 0;
     h->ensure_workspace(LP, bfmode ? 1 : 0);
-    // which inner pass pairs store their panels in BF16: all of them (modes 1 and 3) or all but
-    // the last one, whose basis feeds the final Rayleigh-Ritz step (mode 2); mode 3 stores only
-    // the basis read by the forward product in BF16 and keeps the long-side panel in FP32
+    // which inner pass pairs store panels in BF16: all of them (modes 1 and 3) or all but the
+    // last one, whose basis feeds the final Rayleigh-Ritz step (modes 2 and 4); which panels:
+    // the basis read by the forward product and the long-side panel read by the back product
+    // (modes 1 and 2), only the basis (mode 3) or only the long-side panel (mode 4)
     const int last = (p_passes - 1) / 2;
-    auto bf_pair = [&](int i) { return bfmode == 1 || bfmode == 3 || (bfmode == 2 && i < last); };
-    const bool bf_long = bfmode != 3;  // the long-side panel follows the pass pair's choice
+    auto bf_pair = [&](int i) { return bfmode == 1 || bfmode == 3 || ((bfmode == 2 || bfmode == 4) && i < last); };
+    const bool bf_basis = bfmode != 4;
+    const bool bf_long = bfmode != 3;
     const bool fused = h->opts.fused_pass != 0;
     FRPCA_CHECK(!fused || (!h->opts.center && !bfmode), FRPCA_EINVAL,
                 "opts.fused_pass does not combine with center or panel_bf16");
@@ -658,9 +660,9 @@ int frpca_run(frpca_t h, int k, int p_passes, int s_oversample, uint64_t seed, f
     // forward product (short side -> long side): A Q for Alg. 6, A^T Q for Alg. 5
     auto forward_corr = [&](const void* in, bool in_b) { return a6 ? corr_a(in, in_b) : corr_at(in, in_b); };
     auto forward_inner = [&](bool bf) {
-      if (bf && bf_long) spmm(Fp, fwd_cls, h->Qb, true, nullptr, h->Yb, forward_corr(h->Qb, true));
-      else if (bf) spmm(Fp, fwd_cls, h->Qb, true, h->Y, nullptr, forward_corr(h->Qb, true));
-      else spmm(Fp, fwd_cls, h->Q, false, h->Y, nullptr, forward_corr(h->Q, false));
+      const bool qb = bf && bf_basis, yb = bf && bf_long;
+      const void* in = qb ? static_cast<const void*>(h->Qb) : static_cast<const void*>(h->Q);
+      spmm(Fp, fwd_cls, in, qb, yb ? nullptr : h->Y, yb ? h->Yb : nullptr, forward_corr(in, qb));
     };
     // back product (long side -> short side). For Alg. 6 the panel Y = (A - 1 mu^T) Q of a
     // centred forward product has 1^T Y = (1^T A - m mu^T) Q = 0 exactly, so the term is
@@ -714,10 +716,10 @@ int frpca_run(frpca_t h, int k, int p_passes, int s_oversample, uint64_t seed, f
       }
       back(false, bf0);
       if (p_passes == 2) orth_eig(false);
-      else orth_lu(bf_pair(1));
+      else orth_lu(bf_pair(1) && bf_basis);
     } else {
       frpca_ctx::Scope t(h, FRPCA_T_GAUSS);
-      launch_gaussian(seed, Ns, l, LP, h->Q, last >= 1 && bf_pair(1) ? h->Qb : nullptr, st);
+      launch_gaussian(seed, Ns, l, LP, h->Q, last >= 1 && bf_pair(1) && bf_basis ? h->Qb : nullptr, st);
     }
     for (int i = 1; i <= last; ++i) {
       const bool bf = bf_pair(i);
@@ -729,7 +731,7 @@ int frpca_run(frpca_t h, int k, int p_passes, int s_oversample, uint64_t seed, f
         back(true, bf);
       }
       if (i == last) orth_eig(false);
-      else orth_lu(bf_pair(i + 1));
+      else orth_lu(bf_pair(i + 1) && bf_basis);
     }
     // final pass and Rayleigh-Ritz: eigSVD of the long-side panel Z
     spmm(Fp, fwd_cls, h->Q, false, h->Z, nullptr, forward_corr(h->Q, false));

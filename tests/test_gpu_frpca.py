@@ -119,19 +119,20 @@ def test_sketch_wider_than_128_rejected():
     mat.close()
 
 
-@pytest.mark.parametrize("mode", [1, 2, 3])
+@pytest.mark.parametrize("mode", [1, 2, 3, 4])
 def test_bf16_panel_variants_error_stated(mode):
     """BF16 panels (opts.panel_bf16): 1 every inner pass pair, 2 all but the last one, 3 only the
-    basis read by the forward product. Their error against the FP64 oracle is reported and
-    bounded by the BF16 rounding unit 2^-9 on the singular values and the subspaces; mode 2,
-    whose last inner pass pair (the one that feeds the final Rayleigh-Ritz step) is FP32, stays
-    within 2^-11 on this case (on the 12.9M x 324K workload the benchmark measures 9.6e-5)."""
+    basis read by the forward product, 4 only the long-side panel of all but the last pair.
+    Their error against the FP64 oracle is reported and bounded by the BF16 rounding unit 2^-9
+    on the singular values and the subspaces; modes 2 and 4, whose last inner pass pair (the one
+    that feeds the final Rayleigh-Ritz step) is FP32, stay within 2^-11 on this case (on the
+    12.9M x 324K workload the benchmark measures 9.6e-5 for mode 2 and 2.0e-6 for mode 4)."""
     A = zipf_lognormal(m=30_011, n=4_003, t=40)
     say("bf16 panels, mode", mode)
     r, *_ = check(A, 20, 5, 10, 77, sig_tol=1.0, ang_tol=1.0, panel_bf16=mode)
     say(f"  bf16 mode {mode} error vs FP64 oracle:", r)
     assert r["sig_err"] < 2.0 ** -9 and r["sin_u"] < 2.0 ** -9 * 10 and r["sin_v"] < 2.0 ** -9 * 10
-    if mode == 2:
+    if mode in (2, 4):
         assert r["sig_err"] < 2.0 ** -11
 
 
