@@ -96,6 +96,34 @@ def measured_copy_peak(torch) -> dict:
             "kernel": "torch copy_ of 2 GiB FP32 (2 GiB read + 2 GiB written), best of 10"}
 
 
+def measured_gather_peak(torch, short_rows: int, long_rows: int) -> dict:
+    """Random 512-byte row gathers in the sparse products' lane shape (frpca_gather_probe) from
+    panels of the workload's two sides (128 FP32 columns), best of 3: the ceiling of the
+    products' access pattern beside the streaming copy rate."""
+    from paper_1810_06825_amd import FrPCA, binding
+    from synth import random_sparse
+
+    tiny = FrPCA.from_csr(random_sparse(64, 64, 0.2, seed=1), device="cuda:0")
+    out = torch.zeros(64, dtype=torch.float32, device="cuda:0")
+    rec = {"kernel": "frpca_gather_probe: random rows of 128 FP32 (512 B), float4 per lane, two rows per "
+                     "wave instruction, 8 row pairs in flight per wave; best of 3"}
+    for name, rows in (("short_side_panel", short_rows), ("long_side_panel", long_rows)):
+        P = torch.zeros((rows, 128), dtype=torch.float32, device="cuda:0")
+        gathers = 100_000_000
+        binding.frpca_gather_probe(tiny.h, P, rows, 128, gathers // 10, 7, out)
+        best, nr = float("inf"), 0
+        for it in range(3):
+            ms, nr = binding.frpca_gather_probe(tiny.h, P, rows, 128, gathers, 11 + it, out)
+            best = min(best, ms)
+        gbps = nr * 512 / (best * 1e-3) / 1e9
+        rec[name] = {"rows": rows, "panel_MB": round(rows * 512 / 1e6, 1), "rows_read": nr,
+                     "GBps": round(gbps, 1), "frac_of_nominal": round(gbps / PEAK_HBM_GBPS, 4)}
+        del P
+        torch.cuda.empty_cache()
+    tiny.close()
+    return rec
+
+
 def spmm_source_hash():
     h = hashlib.sha256()
     for f in SPMM_SOURCES:
@@ -544,6 +572,9 @@ def main():
     t0 = time.time()
     A = gen(**kw)
     log(f"generated {args.workload} {A.m}x{A.n} nnz={A.nnz} in {time.time() - t0:.1f}s")
+    gather_peak = None if args.no_extras else measured_gather_peak(torch, min(A.m, A.n), max(A.m, A.n))
+    if gather_peak:
+        log("random row gathers:", gather_peak)
     mat, h = headline(args, A, k, q, s, torch, np)
     ms = h["ms"]
     extras = {}
@@ -596,6 +627,7 @@ def main():
         "spmm": h["spmm"],
         "gram": h["gram"],
         "hbm_copy_measured": copy_peak,
+        "row_gather_measured": gather_peak,
         "create_ms": round(h["create_ms"], 2),
         "per_class_ms": {kk: round(v["ms_total_per_step"], 4) for kk, v in h["per"].items()},
         "ms_per_step_with_class_events": round(h["ms_timers"], 4),

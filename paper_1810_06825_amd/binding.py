@@ -8,7 +8,7 @@ from __future__ import annotations
 
 import ctypes
 import os
-from ctypes import POINTER, c_char_p, c_double, c_int, c_int32, c_int64, c_size_t, c_uint64, c_void_p
+from ctypes import POINTER, c_char_p, c_double, c_float, c_int, c_int32, c_int64, c_size_t, c_uint32, c_uint64, c_void_p
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libfrpca.so")
 
@@ -71,6 +71,8 @@ _SIGNATURES = {
     "frpca_pass": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_int]),
     "frpca_tsmm": (c_int, [c_void_p, c_int64, c_int, c_int, c_void_p, c_int, c_void_p, c_void_p, c_int]),
     "frpca_sddmm": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "frpca_gather_probe": (c_int, [c_void_p, c_void_p, c_int64, c_int, c_int64, c_uint32, c_void_p,
+                                   POINTER(c_float), POINTER(c_int64)]),
     "frpca_export_csc": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
 }
 
@@ -216,6 +218,14 @@ def frpca_pass(h, l, inp, out, fused):
 
 def frpca_tsmm(h, rows, kdim, c, X, ldx, B, out, ldo):
     _check(load().frpca_tsmm(h, rows, kdim, c, _ptr(X), ldx, _ptr(B), _ptr(out), ldo), h)
+
+
+def frpca_gather_probe(h, P, rows, ld, gathers, seed, out):
+    """Random 512-byte row reads of P; returns (ms, rows_read)."""
+    ms, nr = c_float(0.0), c_int64(0)
+    _check(load().frpca_gather_probe(h, _ptr(P), rows, ld, gathers, seed, _ptr(out), ctypes.byref(ms),
+                                     ctypes.byref(nr)), h)
+    return ms.value, nr.value
 
 
 def frpca_sddmm(h, w, P1, Q1, P2, Q2, dval):

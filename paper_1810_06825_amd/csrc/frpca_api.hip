@@ -1389,6 +1389,30 @@ int frpca_tsmm(frpca_t h, int64_t rows, int kdim, int c, const float* X, int ldx
   });
 }
 
+int frpca_gather_probe(frpca_t h, const float* P, int64_t rows, int ld, int64_t gathers, uint32_t seed,
+                       float* out, float* ms, int64_t* rows_read) {
+  if (!h) return fail(nullptr, Error{FRPCA_EINVAL, "NULL handle"});
+  return guarded(h, [&] {
+    FRPCA_CHECK(P && out && ms && rows >= 1 && rows <= 0xFFFFFFFFll && ld >= 128 && (ld & 3) == 0 &&
+                    (reinterpret_cast<uintptr_t>(P) & 15) == 0 && gathers >= 1 && gathers <= (int64_t)1 << 40,
+                FRPCA_EINVAL, "bad gather probe arguments");
+    hipEvent_t e0, e1;
+    FRPCA_HIP(hipEventCreate(&e0));
+    FRPCA_HIP(hipEventCreate(&e1));
+    FRPCA_HIP(hipEventRecord(e0, h->stream));
+    launch_gather_probe(P, rows, ld, gathers, seed, out, h->stream);
+    check_launch();
+    FRPCA_HIP(hipEventRecord(e1, h->stream));
+    FRPCA_HIP(hipEventSynchronize(e1));
+    float t = 0.f;
+    FRPCA_HIP(hipEventElapsedTime(&t, e0, e1));
+    FRPCA_HIP(hipEventDestroy(e0));
+    FRPCA_HIP(hipEventDestroy(e1));
+    *ms = t;
+    if (rows_read) *rows_read = gather_probe_rows(gathers);
+  });
+}
+
 int frpca_sddmm(frpca_t h, int w, const float* P1, const float* Q1, const float* P2, const float* Q2,
                 float* dval) {
   if (!h) return fail(nullptr, Error{FRPCA_EINVAL, "NULL handle"});

@@ -369,3 +369,19 @@ def test_sddmm_matches_row_dots():
     ref = (P1[rows].astype(np.float64) * Q1[c]).sum(1) + (P2[rows].astype(np.float64) * Q2[c]).sum(1)
     bound = (np.abs(P1[rows]) * np.abs(Q1[c])).sum(1) + (np.abs(P2[rows]) * np.abs(Q2[c])).sum(1)
     assert np.all(np.abs(np64(d) - ref) <= 1e-6 * bound + 1e-30)
+
+
+def test_gather_probe_runs_and_checks_arguments():
+    """The measurement helper behind the bench's row-gather ceiling: it reads whole waves of
+    random rows (the count it reports), leaves a zero panel's sum unobserved and rejects panels
+    narrower than a 512-byte row."""
+    say("gather probe")
+    mat = _mat(random_sparse(8, 8, 0.5, seed=1))
+    P = torch.zeros((1000, 128), dtype=torch.float32, device=DEV)
+    out = torch.full((64,), 3.0, dtype=torch.float32, device=DEV)
+    ms, nr = binding.frpca_gather_probe(mat.h, P, 1000, 128, 5000, 1, out)
+    assert ms > 0 and nr >= 5000 and nr % 512 == 0
+    assert torch.all(out == 3.0)
+    with pytest.raises(binding.FrpcaError):
+        binding.frpca_gather_probe(mat.h, P, 1000, 64, 5000, 1, out)
+    mat.close()
