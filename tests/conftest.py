@@ -12,6 +12,9 @@ if HERE not in sys.path:
 
 
 def pytest_configure(config):
+    import gpu_util
+
+    gpu_util.CAPTURE_MANAGER = config.pluginmanager.getplugin("capturemanager")
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: full-size workloads (minutes of CPU)")
 

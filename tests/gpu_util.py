@@ -10,8 +10,18 @@ ANG_TOL = 1e-3    # largest principal angle, radians (sine used; equal to 1e-9 r
 GAP_MIN = 1e-2    # relative Ritz gap below which a leading block is not separable
 
 
+# pytest's capture manager, set by conftest: say() prints past the capture, so the steps of a
+# long test (a full-size oracle run takes minutes) show as they happen
+CAPTURE_MANAGER = None
+
+
 def say(*a):
-    print("[gpu-test]", *a, flush=True)
+    capman = CAPTURE_MANAGER
+    if capman is not None:
+        with capman.global_and_fixture_disabled():
+            print("[gpu-test]", *a, flush=True)
+    else:
+        print("[gpu-test]", *a, flush=True)
     sys.stdout.flush()
 
 
