@@ -287,7 +287,7 @@ def headline(args, A, k, q, s, torch, np):
 
 def variants(A, k, q, s, steps, torch, np, S_ref):
     """BF16 panels (every inner pass pair, all but the last one, or the long-side panel of all
-    but the last one), the FP32-MFMA Gram, the
+    but the last one), the FP32-MFMA Gram, the final products on FP64 MFMA, the
     one-sweep pass pairs with atomic adds and the centred run on the headline matrix: time and
     singular-value difference against the default FP32 path."""
     from paper_1810_06825_amd import FrPCA
@@ -297,7 +297,8 @@ def variants(A, k, q, s, steps, torch, np, S_ref):
     n = max(3, steps // 2)
     for name, kw in (("bf16_panel", {"panel_bf16": 1}), ("bf16_mixed", {"panel_bf16": 2}),
                      ("bf16_long", {"panel_bf16": 4}), ("gram_f32", {"gram_f32": True}),
-                     ("fused_pass", {"fused_pass": True}), ("centered", {"center": True})):
+                     ("final_f64", {"final_f64": True}), ("fused_pass", {"fused_pass": True}),
+                     ("centered", {"center": True})):
         m2 = FrPCA.from_csr(A, device="cuda:0", **kw)
         t, (_, S2, _) = timed_runs(m2, k, q, s, n, 1, torch)
         m2.close()

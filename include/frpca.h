@@ -91,6 +91,12 @@ typedef struct {
                            The order of the atomic adds varies, so results are not bitwise
                            repeatable; not with center or panel_bf16. 0 (default): the two
                            deterministic products of the merge-path plans.            */
+  int final_f64;        /* 1: the final products that form the outputs (U and V from the
+                           last panels and the l x k coefficient matrices) accumulate on
+                           the FP64 matrix cores. 0 (default): on the FP32 matrix cores at
+                           twice the rate, the coefficients rounded to FP32; their
+                           matrices are orthogonal or scaled by 1/sigma, so the outputs move
+                           by about one FP32 rounding per term (orthonormality ~1e-7). */
 } frpca_opts;
 
 typedef struct {

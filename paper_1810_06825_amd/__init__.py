@@ -35,7 +35,7 @@ class FrPCA:
     def __init__(self, row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, shape,
                  panel_bf16: int = 0, sign_fix: bool = True, rank_tol: float = 0.0,
                  timing: bool = False, max_workspace: int = 0, center: bool = False,
-                 gram_f32: bool = False, fused_pass: bool = False):
+                 gram_f32: bool = False, fused_pass: bool = False, final_f64: bool = False):
         assert row_ptr.is_cuda and col.is_cuda and val.is_cuda
         assert row_ptr.dtype == torch.int64 and col.dtype == torch.int32 and val.dtype == torch.float32
         self.row_ptr = row_ptr.contiguous()
@@ -45,7 +45,7 @@ class FrPCA:
         self.nnz = int(self.col.numel())
         self.device = self.val.device
         opts = FrpcaOpts(int(panel_bf16), int(not sign_fix), float(rank_tol), int(timing), int(max_workspace),
-                         int(center), int(gram_f32), int(fused_pass))
+                         int(center), int(gram_f32), int(fused_pass), int(final_f64))
         self.h = binding.frpca_create(self.m, self.n, self.nnz, self.row_ptr, self.col, self.val, opts,
                                       _stream())
         self.run_id = 0      # runs so far; frpca_backward refers to the last one

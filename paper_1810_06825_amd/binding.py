@@ -32,7 +32,7 @@ class FrpcaError(RuntimeError):
 class FrpcaOpts(ctypes.Structure):
     _fields_ = [("panel_bf16", c_int), ("no_sign_fix", c_int), ("rank_tol", c_double),
                 ("timing", c_int), ("max_workspace", c_size_t), ("center", c_int),
-                ("gram_f32", c_int), ("fused_pass", c_int)]
+                ("gram_f32", c_int), ("fused_pass", c_int), ("final_f64", c_int)]
 
 
 class FrpcaInfo(ctypes.Structure):

@@ -742,11 +742,13 @@ int frpca_run(frpca_t h, int k, int p_passes, int s_oversample, uint64_t seed, f
     float* out_short = a6 ? V : U;
     auto tsmm_long = [&] {
       frpca_ctx::Scope t(h, FRPCA_T_TSMM);
-      launch_tsmm(h->Z, false, LP, Nl, l, h->B1, LP, k, k, out_long, k, nullptr, 0, st);
+      launch_tsmm(h->Z, false, LP, Nl, l, h->B1, LP, k, k, out_long, k, nullptr, 0, st, nullptr, 0, nullptr, 0,
+                  !h->opts.final_f64);
     };
     auto tsmm_short = [&] {
       frpca_ctx::Scope t(h, FRPCA_T_TSMM);
-      launch_tsmm(h->Q, false, LP, Ns, l, h->B2, LP, k, k, out_short, k, nullptr, 0, st);
+      launch_tsmm(h->Q, false, LP, Ns, l, h->B2, LP, k, k, out_short, k, nullptr, 0, st, nullptr, 0, nullptr, 0,
+                  !h->opts.final_f64);
     };
     if (a6) {  // V is the short-side output: build it, fix signs, then U
       tsmm_short();
@@ -856,7 +858,7 @@ int frpca_run_basic(frpca_t h, int k, int p_power, int s_oversample, uint64_t se
     double* Bv = u_on_S ? Bo : Bs;
     {
       frpca_ctx::Scope t(h, FRPCA_T_TSMM);
-      launch_tsmm(Pv, false, LP, n, l, Bv, LP, k, k, V, k, nullptr, 0, st);
+      launch_tsmm(Pv, false, LP, n, l, Bv, LP, k, k, V, k, nullptr, 0, st, nullptr, 0, nullptr, 0, !h->opts.final_f64);
     }
     if (!h->opts.no_sign_fix) {
       frpca_ctx::Scope t(h, FRPCA_T_SIGN);
@@ -864,7 +866,7 @@ int frpca_run_basic(frpca_t h, int k, int p_power, int s_oversample, uint64_t se
     }
     {
       frpca_ctx::Scope t(h, FRPCA_T_TSMM);
-      launch_tsmm(Pu, false, LP, m, l, Bu, LP, k, k, U, k, nullptr, 0, st);
+      launch_tsmm(Pu, false, LP, m, l, Bu, LP, k, k, U, k, nullptr, 0, st, nullptr, 0, nullptr, 0, !h->opts.final_f64);
     }
     check_launch();
     h->info.k = k;
@@ -1029,8 +1031,8 @@ int frpca_eigsvds(frpca_t h, int k, int s_oversample, uint64_t seed, double tol,
     float* out_short = a6 ? V : U;
     {
       frpca_ctx::Scope t(h, FRPCA_T_TSMM);
-      if (a6) launch_tsmm(Qc, false, LP, Ns, l, h->B2, LP, k, k, out_short, k, nullptr, 0, st);
-      else launch_tsmm(h->Z, false, LP, Nl, l, h->B1, LP, k, k, out_long, k, nullptr, 0, st);
+      if (a6) launch_tsmm(Qc, false, LP, Ns, l, h->B2, LP, k, k, out_short, k, nullptr, 0, st, nullptr, 0, nullptr, 0, !h->opts.final_f64);
+      else launch_tsmm(h->Z, false, LP, Nl, l, h->B1, LP, k, k, out_long, k, nullptr, 0, st, nullptr, 0, nullptr, 0, !h->opts.final_f64);
     }
     if (!h->opts.no_sign_fix) {
       frpca_ctx::Scope t(h, FRPCA_T_SIGN);
@@ -1039,8 +1041,8 @@ int frpca_eigsvds(frpca_t h, int k, int s_oversample, uint64_t seed, double tol,
     }
     {
       frpca_ctx::Scope t(h, FRPCA_T_TSMM);
-      if (a6) launch_tsmm(h->Z, false, LP, Nl, l, h->B1, LP, k, k, out_long, k, nullptr, 0, st);
-      else launch_tsmm(Qc, false, LP, Ns, l, h->B2, LP, k, k, out_short, k, nullptr, 0, st);
+      if (a6) launch_tsmm(h->Z, false, LP, Nl, l, h->B1, LP, k, k, out_long, k, nullptr, 0, st, nullptr, 0, nullptr, 0, !h->opts.final_f64);
+      else launch_tsmm(Qc, false, LP, Ns, l, h->B2, LP, k, k, out_short, k, nullptr, 0, st, nullptr, 0, nullptr, 0, !h->opts.final_f64);
     }
     check_launch();
     h->info.k = k;

@@ -120,11 +120,13 @@ void launch_gram(const void* X1, bool bf16, int ld1, const float* X2, int ld2, i
                  int l, double* partial, double* G, int ldg, hipStream_t st, bool f32_mfma = false);
 // out[rows x c_out] = X[rows x kdim] B[kdim x c] (+ y2 diag(d2) when y2 is given); columns
 // c..c_out-1 written as 0. FP64 MFMA accumulation, the y2 term added in FP64 before the one
-// rounding to FP32. out (optional) and out_bf16 (optional) receive FP32 and BF16 results.
+// rounding to FP32; with f32_mfma (FP32 X only), B rounded to FP32 and FP32 MFMA accumulation at
+// twice the rate, for well-conditioned B. out (optional) and out_bf16 (optional) receive FP32
+// and BF16 results.
 void launch_tsmm(const void* X, bool x_bf16, int ldx, int64_t rows, int kdim, const double* B,
                  int ldb, int c, int c_out, float* out, int ldo, uint16_t* out_bf16, int ldo16,
                  hipStream_t st, const float* y2 = nullptr, int ldy2 = 0, const double* d2 = nullptr,
-                 int ldd2 = 0);
+                 int ldd2 = 0, bool f32_mfma = false);
 
 // Symmetric eigendecomposition (G: l x l FP64, ldg): Householder tridiagonalization, then
 // relatively robust representations (three launches). d ascending, W l x l row-major

@@ -136,6 +136,28 @@ def test_bf16_panel_variants_error_stated(mode):
         assert r["sig_err"] < 2.0 ** -11
 
 
+@pytest.mark.parametrize("shape", ["tall", "wide"])
+def test_final_products_fp32_against_fp64(shape):
+    """The outputs' final products on the FP32 matrix cores (default) against the FP64 form
+    (opts.final_f64): the same singular values (they come from the FP64 eigensolver), factors
+    within a few FP32 roundings per term of each other, orthonormal to 1e-6, and both within
+    the oracle tolerances."""
+    A, k, q, s, seed = {"tall": (zipf_lognormal(m=30_011, n=4_003, t=40), 20, 5, 10, 77),
+                        "wide": (zipf_normal(m=3_001, n=20_011, t=30), 16, 4, 8, 99)}[shape]
+    r32, (U32, S32, V32), *_ = check(A, k, q, s, seed)
+    r64, (U64, S64, V64), *_ = check(A, k, q, s, seed, final_f64=True)
+    assert r32["ok"] and r64["ok"]
+    assert np.array_equal(S32, S64)
+    # the sign rule reads the largest entry of each v_i: a near-tie may resolve differently
+    sg = np.sign(np.sum(V32 * V64, axis=0))
+    du = np.abs(U32 * sg - U64).max() / np.abs(U64).max()
+    dv = np.abs(V32 * sg - V64).max() / np.abs(V64).max()
+    say(f"  FP32 vs FP64 final products: U {du:.2e}, V {dv:.2e}")
+    assert du < 1e-5 and dv < 1e-5
+    for M in (U32, V32):
+        assert np.abs(M.T @ M - np.eye(k)).max() < 1e-6
+
+
 @pytest.mark.parametrize("case", ["small_decay", "zipf_tall", "zipf_wide"])
 def test_gram_f32_variant_error_stated(case):
     """eigSVD's Gram on the FP32 matrix cores (opts.gram_f32): its error against the FP64
