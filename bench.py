@@ -361,6 +361,50 @@ def secondary_zipf(args, torch, np):
     return rec
 
 
+def planted_cfg(args, torch, np):
+    """The planted-spectrum workload: 200,000 x 50,000 (50M nnz, 250 per row), exact
+    sigma_i = 10^(-3 i / 200) on 200 disjoint blocks, k = 100, s = 20. The default path at
+    q = 2, 3, 5, 7 and, at q = 5, the precision variants (BF16 panels, FP32-MFMA Gram, FP64
+    final products), each with its sigma error against the exact spectrum and its difference
+    from the default path."""
+    from paper_1810_06825_amd import FrPCA
+    from synth import WORKLOADS
+
+    gen, kw, k, s, q0 = WORKLOADS["planted_blocks"]
+    A = gen(**kw)
+    exact = np.asarray(A.meta["sigma"], dtype=np.float64)[:k]
+
+    def errs(S):
+        S = S.double().cpu().numpy()
+        r = np.abs(S - exact) / exact
+        return S, {"sigma_rel_err_top10": float(r[:10].max()), "sigma_rel_err_top100": float(r.max())}
+
+    rec = {"workload": f"planted_blocks {A.m}x{A.n} CSR, {A.nnz} nnz", "k": k, "s": s, "passes": {}}
+    n = max(3, args.steps // 2)
+    mat = FrPCA.from_csr(A, device="cuda:0")
+    S5 = None
+    for q in (2, 3, 5, 7):
+        t, (_, S, _) = timed_runs(mat, k, q, s, n, 1, torch)
+        Sq, e = errs(S)
+        rec["passes"][f"q{q}"] = {"ms": round(t, 3), **e}
+        if q == 5:
+            S5 = Sq
+    mat.close()
+    rec["variants_q5"] = {}
+    for name, vkw in (("bf16_panel", {"panel_bf16": 1}), ("bf16_mixed", {"panel_bf16": 2}),
+                      ("bf16_long", {"panel_bf16": 4}), ("gram_f32", {"gram_f32": True}),
+                      ("final_f64", {"final_f64": True})):
+        mv = FrPCA.from_csr(A, device="cuda:0", **vkw)
+        t, (_, S, _) = timed_runs(mv, k, 5, s, n, 1, torch)
+        mv.close()
+        Sv, e = errs(S)
+        rec["variants_q5"][name] = {"ms": round(t, 3), **e,
+                                    "sigma_rel_diff_vs_default": float(np.max(np.abs(Sv - S5) / S5))}
+    log("planted_blocks:", json.dumps(rec))
+    free(torch)
+    return rec
+
+
 def differentiated(args, torch, np):
     """The differentiated workload: 500,000 x 100,000, 30 per row, Zipf 1.1, N(0,1) values,
     k = 50, s = 10, q = 4, loss = sum(sigma) + ||U W||^2 (W 50 x 8, seed 7). Forward alone
@@ -593,9 +637,10 @@ def main():
     mat.close()
     del U, S, V, h["factors"]
     free(torch)
-    secondary = diff = eigs = None
+    secondary = diff = eigs = planted = None
     if not args.no_extras:
         secondary = secondary_zipf(args, torch, np)
+        planted = planted_cfg(args, torch, np)
         diff = differentiated(args, torch, np)
         eigs = eigsvds_vs_fast(torch, np)
     cpu = None
@@ -635,6 +680,7 @@ def main():
         **extras,
         "variants": var or None,
         "zipf_lognormal": secondary,
+        "planted_blocks": planted,
         "differentiated": diff,
         "basic_vs_fast": basic,
         "eigsvds_vs_fast": eigs,
