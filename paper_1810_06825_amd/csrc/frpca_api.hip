@@ -493,6 +493,8 @@ int frpca_create(frpca_t* out, int64_t m, int64_t n, int64_t nnz, const int64_t*
       check_launch();
       h->build_plan(h->csr, h->rp32, col, val, m);
       h->build_plan(h->csc, h->cp32, h->row_csc, h->val_csc, n);
+      h->csr.in_rows = n;  // the forward product over rows gathers rows of an n-row panel
+      h->csc.in_rows = m;
       if (h->opts.center) {
         h->mu = static_cast<float*>(h->alloc_owned(std::max<int64_t>(n, 1) * sizeof(float)));
         launch_colmean(h->cp32, h->val_csc, n, m, h->mu, st);
@@ -549,6 +551,7 @@ int frpca_create(frpca_t* out, int64_t m, int64_t n, int64_t nnz, const int64_t*
           h->build_plan(h->btailp, h->bptr_tail, h->brow + nnz_hot, h->bval + nnz_hot, n - hh, false,
                         nnz - nnz_hot);
           h->btailp.out_row = h->btailcol;  // tail segment i is column btailcol[i] of the result
+          h->bhotp.in_rows = h->btailp.in_rows = m;
           check_launch();
         }
       }

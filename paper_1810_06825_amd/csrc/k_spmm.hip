@@ -231,14 +231,26 @@ constexpr int kPairs = FRPCA_SPMM_PAIRS;  // pairs per batch; two batches in fli
 #define FRPCA_SPMM_NT_STORE 1
 #endif
 
-template <bool IN_BF16>
+// NT: streaming (non-temporal) gathers, for panels so much larger than the Infinity Cache
+// that a gathered row is almost never found there again
+template <bool IN_BF16, bool NT>
 __device__ __forceinline__ float4 load4(const void* base, size_t idx) {
   if constexpr (IN_BF16) {
-    const uint2 w = *reinterpret_cast<const uint2*>(static_cast<const uint16_t*>(base) + idx);
+    typedef unsigned int v2u __attribute__((ext_vector_type(2)));
+    const v2u* q = reinterpret_cast<const v2u*>(static_cast<const uint16_t*>(base) + idx);
+    v2u w;
+    if constexpr (NT) w = __builtin_nontemporal_load(q);
+    else w = *q;
     return make_float4(__uint_as_float(w.x << 16), __uint_as_float(w.x & 0xFFFF0000u), __uint_as_float(w.y << 16),
                        __uint_as_float(w.y & 0xFFFF0000u));
   } else {
-    return *reinterpret_cast<const float4*>(static_cast<const float*>(base) + idx);
+    if constexpr (NT) {
+      typedef float v4f __attribute__((ext_vector_type(4)));
+      const v4f t = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(static_cast<const float*>(base) + idx));
+      return make_float4(t.x, t.y, t.z, t.w);
+    } else {
+      return *reinterpret_cast<const float4*>(static_cast<const float*>(base) + idx);
+    }
   }
 }
 
@@ -249,7 +261,7 @@ __device__ __forceinline__ void fma4(float4& acc, float v, const float4& x) {
   acc.w = fmaf(v, x.w, acc.w);
 }
 
-template <bool IN_BF16>
+template <bool IN_BF16, bool NT>
 __device__ __forceinline__ void spmm_partition4(const SpmmArgs& a, int64_t w, int lane, int* lw) {
   const int half = lane >> 5;
   const int col = 4 * (lane & 31);
@@ -370,7 +382,7 @@ __device__ __forceinline__ void spmm_partition4(const SpmmArgs& a, int64_t w, in
         const int c = __shfl(widx, src & 63);
         const float vv = __shfl(wval, src & 63);
         v[p] = valid ? vv : 0.f;
-        x[p] = load4<IN_BF16>(a.in, (size_t)(valid ? c : 0) * a.ld_in + gcol);
+        x[p] = load4<IN_BF16, NT>(a.in, (size_t)(valid ? c : 0) * a.ld_in + gcol);
       }
       consume();
 #pragma unroll
@@ -395,10 +407,10 @@ __device__ __forceinline__ void spmm_partition4(const SpmmArgs& a, int64_t w, in
   }
 }
 
-template <bool IN_BF16>
 #ifndef FRPCA_SPMM_MINW
 #define FRPCA_SPMM_MINW 1
 #endif
+template <bool IN_BF16, bool NT>
 __global__ __launch_bounds__(256, FRPCA_SPMM_MINW) void spmm_merge4_kernel(SpmmArgs a) {
   __shared__ int win[4][128];  // per wave: 64 segment ends, then 64 output rows
   const int lane = threadIdx.x & 63;
@@ -406,13 +418,13 @@ __global__ __launch_bounds__(256, FRPCA_SPMM_MINW) void spmm_merge4_kernel(SpmmA
   int* lw = win[wv];
   if (!a.sweep) {
     const int64_t w = (int64_t)blockIdx.x * 4 + wv;
-    if (w < a.nwaves) spmm_partition4<IN_BF16>(a, w, lane, lw);
+    if (w < a.nwaves) spmm_partition4<IN_BF16, NT>(a, w, lane, lw);
     return;
   }
   for (int64_t round = 0;; ++round) {
     const int64_t w = sweep_block(round) * 4 + wv;
     if (w >= a.nwaves) break;
-    spmm_partition4<IN_BF16>(a, w, lane, lw);
+    spmm_partition4<IN_BF16, NT>(a, w, lane, lw);
   }
 }
 
@@ -467,8 +479,16 @@ void launch_spmm_main(const MergePlan& p, int lp, const void* in, bool in_bf16, 
   const bool al_out = (!out_f32 || (reinterpret_cast<uintptr_t>(out_f32) % 16) == 0) &&
                       (!out_bf16 || (reinterpret_cast<uintptr_t>(out_bf16) % 8) == 0) && (ld_out % 4) == 0;
   if ((lp % 4) == 0 && al_in && al_out) {
-    if (in_bf16) spmm_merge4_kernel<true><<<grid, 256, 0, st>>>(a);
-    else spmm_merge4_kernel<false><<<grid, 256, 0, st>>>(a);
+    // streaming gathers for a panel many times the Infinity Cache (not in sweep mode, whose
+    // gathered rows are meant to stay in L2)
+    const bool nt = !p.sweep && p.in_rows > 0 && (double)p.in_rows * ld_in * ein > kStreamPanelBytes;
+    if (in_bf16) {
+      if (nt) spmm_merge4_kernel<true, true><<<grid, 256, 0, st>>>(a);
+      else spmm_merge4_kernel<true, false><<<grid, 256, 0, st>>>(a);
+    } else {
+      if (nt) spmm_merge4_kernel<false, true><<<grid, 256, 0, st>>>(a);
+      else spmm_merge4_kernel<false, false><<<grid, 256, 0, st>>>(a);
+    }
     return;
   }
   if (in_bf16) spmm_merge_kernel<true><<<grid, 256, 0, st>>>(a);
