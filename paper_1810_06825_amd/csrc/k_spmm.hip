@@ -429,38 +429,56 @@ __global__ __launch_bounds__(256, FRPCA_SPMM_MINW) void spmm_merge4_kernel(SpmmA
 }
 
 // out[c] = carry[w0] + ... + carry[w1-1] + head[w1] for segments cut by partition bounds
-// (row c of out, or row out_row[c] when the plan maps segments to output rows).
-__global__ __launch_bounds__(256) void spmm_fixup_kernel(const int32_t* part_seg, const int32_t* fix_w0,
-                                                         int64_t nwaves, const float* carry, const float* head,
-                                                         float* out_f32, uint16_t* out_bf16, int ld_out, int lp,
-                                                         const int32_t* out_row, const float* csub_v,
-                                                         const float* csub_s) {
+// (row c of out, or row out_row[c] when the plan maps segments to output rows). A wave takes
+// kFixPerWave consecutive partitions (one launch-sized block per partition was bound by block
+// dispatch, most partitions ending a single cut row).
+constexpr int kFixPerWave = 8;
+__global__ __launch_bounds__(256) void spmm_fixup_kernel(const int32_t* __restrict__ part_seg,
+                                                         const int32_t* __restrict__ fix_w0, int64_t nwaves,
+                                                         const float* __restrict__ carry,
+                                                         const float* __restrict__ head, float* __restrict__ out_f32,
+                                                         uint16_t* __restrict__ out_bf16, int ld_out, int lp,
+                                                         const int32_t* __restrict__ out_row,
+                                                         const float* __restrict__ csub_v,
+                                                         const float* __restrict__ csub_s) {
   const int lane = threadIdx.x & 63;
-  const int64_t w1 = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (w1 >= nwaves) return;
-  const int w0 = fix_w0[w1];
-  if (w0 < 0) return;
   const int col = 2 * lane;
   if (col >= lp) return;
-  const int c = part_seg[w1];
-  float2 s = make_float2(0.f, 0.f);
-  for (int64_t w = w0; w < w1; ++w) {
-    const float2 t = *reinterpret_cast<const float2*>(carry + (size_t)w * 128 + col);
-    s.x += t.x;
-    s.y += t.y;
+  const int64_t wave = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t wbeg = wave * kFixPerWave;
+  // the partitions' bounds first, so their loads are in flight together
+  int w0s[kFixPerWave], cs[kFixPerWave];
+#pragma unroll
+  for (int k = 0; k < kFixPerWave; ++k) {
+    const bool in = wbeg + k < nwaves;
+    w0s[k] = in ? fix_w0[wbeg + k] : -1;
+    cs[k] = in ? part_seg[wbeg + k] : 0;
   }
-  const float2 h = *reinterpret_cast<const float2*>(head + (size_t)w1 * 128 + col);
-  s.x += h.x;
-  s.y += h.y;
-  const int64_t orow = out_row ? out_row[c] : c;
-  if (csub_v) {
-    const float sc = csub_s ? csub_s[orow] : 1.f;
-    s.x -= sc * csub_v[col];
-    s.y -= sc * csub_v[col + 1];
+#pragma unroll
+  for (int k = 0; k < kFixPerWave; ++k) {
+    const int64_t w1 = wbeg + k;
+    const int w0 = w0s[k];
+    if (w0 < 0) continue;
+    const float2 h = *reinterpret_cast<const float2*>(head + (size_t)w1 * 128 + col);
+    float2 s = make_float2(0.f, 0.f);
+    for (int64_t w = w0; w < w1; ++w) {
+      const float2 t = *reinterpret_cast<const float2*>(carry + (size_t)w * 128 + col);
+      s.x += t.x;
+      s.y += t.y;
+    }
+    s.x += h.x;
+    s.y += h.y;
+    const int c = cs[k];
+    const int64_t orow = out_row ? out_row[c] : c;
+    if (csub_v) {
+      const float sc = csub_s ? csub_s[orow] : 1.f;
+      s.x -= sc * csub_v[col];
+      s.y -= sc * csub_v[col + 1];
+    }
+    const size_t o = (size_t)orow * ld_out + col;
+    if (out_f32) store2_f32(out_f32, o, s);
+    if (out_bf16) store2_bf16(out_bf16, o, s);
   }
-  const size_t o = (size_t)orow * ld_out + col;
-  if (out_f32) store2_f32(out_f32, o, s);
-  if (out_bf16) store2_bf16(out_bf16, o, s);
 }
 
 }  // namespace
@@ -498,7 +516,8 @@ void launch_spmm_main(const MergePlan& p, int lp, const void* in, bool in_bf16, 
 void launch_spmm_fixup(const MergePlan& p, int lp, float* out_f32, uint16_t* out_bf16, int ld_out, hipStream_t st,
                        SpmmCorr corr) {
   if (p.nwaves <= 0) return;
-  const unsigned grid = (unsigned)((p.nwaves + 3) / 4);
+  const int64_t fwaves = (p.nwaves + kFixPerWave - 1) / kFixPerWave;
+  const unsigned grid = (unsigned)((fwaves + 3) / 4);
   spmm_fixup_kernel<<<grid, 256, 0, st>>>(p.part_seg, p.fix_w0, p.nwaves, p.carry, p.head, out_f32, out_bf16,
                                           ld_out, lp, p.out_row, corr.v, corr.s);
 }
