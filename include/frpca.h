@@ -327,7 +327,7 @@ int frpca_export_csc(frpca_t h, int64_t* col_ptr, int32_t* row, int32_t* perm);
  * (device float[rows*ld], ld >= 128 and a multiple of 4, 16-byte aligned), two rows per wave
  * instruction as in the sparse products, on the handle's stream; *ms (host) receives the
  * kernel's time from HIP events and *rows_read (host, optional) the number of rows read
- * (gathers rounded up to whole waves). out: device float[64], scratch that the kernel may
+ * (gathers rounded up to whole workgroups of 2048). out: device float[64], scratch the kernel may
  * write. Synchronous. The rate rows_read * 512 B / ms is the ceiling of the products' gathers
  * beside the streaming peak. Errors: EINVAL, EHIP. */
 int frpca_gather_probe(frpca_t h, const float* P, int64_t rows, int ld, int64_t gathers, uint32_t seed,

@@ -39,17 +39,18 @@ __global__ __launch_bounds__(256) void gather_probe_kernel(const float* P, int64
 
 }  // namespace
 
+// rows read per workgroup: four waves, each 32 batches of 8 row pairs
+constexpr int64_t kProbeRowsPerBlock = 4 * 2 * (int64_t)kProbeBatch * 32;
+
 int64_t gather_probe_rows(int64_t gathers) {
-  const int64_t per_wave = 2 * (int64_t)kProbeBatch * 32;  // rows per wave: 32 batches of 8 pairs
-  const int64_t waves = std::max<int64_t>(1, (gathers + per_wave - 1) / per_wave);
-  return waves * per_wave;
+  const int64_t blocks = std::max<int64_t>(1, (gathers + kProbeRowsPerBlock - 1) / kProbeRowsPerBlock);
+  return blocks * kProbeRowsPerBlock;
 }
 
 void launch_gather_probe(const float* P, int64_t rows, int ld, int64_t gathers, uint32_t seed, float* out,
                          hipStream_t st) {
-  const int pairs_per_wave = kProbeBatch * 32;
-  const int64_t waves = gather_probe_rows(gathers) / (2 * pairs_per_wave);
-  gather_probe_kernel<<<(unsigned)((waves + 3) / 4), 256, 0, st>>>(P, rows, ld, pairs_per_wave, seed, -1.0e38f, out);
+  const int64_t blocks = gather_probe_rows(gathers) / kProbeRowsPerBlock;
+  gather_probe_kernel<<<(unsigned)blocks, 256, 0, st>>>(P, rows, ld, kProbeBatch * 32, seed, -1.0e38f, out);
 }
 
 }  // namespace frpca

@@ -174,8 +174,8 @@ void launch_jacobi_svd(const double* R, int l, double tol, double* d, double* W,
 
 // ---------------------------------------------------------------- gather ceiling (k_probe.hip)
 // Random 512-byte row reads of P (rows x ld floats, ld >= 128, 16-byte aligned rows) in the
-// products' lane shape; gather_probe_rows(g) is the number actually read (g rounded up to
-// whole waves). out: 64 floats, written only if a sum hits an impossible value.
+// products' lane shape; gather_probe_rows(g) is the number actually read (g rounded up to a
+// multiple of 2048, whole workgroups). out: 64 floats, written only if a sum hits an impossible value.
 int64_t gather_probe_rows(int64_t gathers);
 void launch_gather_probe(const float* P, int64_t rows, int ld, int64_t gathers, uint32_t seed, float* out,
                          hipStream_t st);

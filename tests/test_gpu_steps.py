@@ -380,7 +380,7 @@ def test_gather_probe_runs_and_checks_arguments():
     P = torch.zeros((1000, 128), dtype=torch.float32, device=DEV)
     out = torch.full((64,), 3.0, dtype=torch.float32, device=DEV)
     ms, nr = binding.frpca_gather_probe(mat.h, P, 1000, 128, 5000, 1, out)
-    assert ms > 0 and nr >= 5000 and nr % 512 == 0
+    assert ms > 0 and nr >= 5000 and nr % 2048 == 0
     assert torch.all(out == 3.0)
     with pytest.raises(binding.FrpcaError):
         binding.frpca_gather_probe(mat.h, P, 1000, 64, 5000, 1, out)
