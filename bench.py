@@ -38,6 +38,9 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+EXTRAS = ("peaks", "passes", "variants", "basic", "zipf", "planted", "differentiated", "eigsvds")
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -50,6 +53,8 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true", help="same as --cpu-baseline none")
     p.add_argument("--no-extras", action="store_true",
                    help="only the headline timing (profiling runs): no pass sweep, variants or other workloads")
+    p.add_argument("--extra", action="append", choices=EXTRAS, default=None,
+                   help="run only the named extras (repeatable; default: all of them unless --no-extras)")
     p.add_argument("--gram-f32", action="store_true",
                    help="time the variant whose eigSVD Gram runs on the FP32 matrix cores (profiling runs)")
     p.add_argument("--copy-calibration", action="store_true",
@@ -611,13 +616,16 @@ def main():
     gen, kw, k, s, q = WORKLOADS[args.workload]
     if args.passes:
         q = args.passes
-    copy_peak = None if args.no_extras else measured_copy_peak(torch)
+    def want(name):
+        return not args.no_extras and (args.extra is None or name in args.extra)
+
+    copy_peak = measured_copy_peak(torch) if want("peaks") else None
     if copy_peak:
         log("device copy:", copy_peak)
     t0 = time.time()
     A = gen(**kw)
     log(f"generated {args.workload} {A.m}x{A.n} nnz={A.nnz} in {time.time() - t0:.1f}s")
-    gather_peak = None if args.no_extras else measured_gather_peak(torch, min(A.m, A.n), max(A.m, A.n))
+    gather_peak = measured_gather_peak(torch, min(A.m, A.n), max(A.m, A.n)) if want("peaks") else None
     if gather_peak:
         log("random row gathers:", gather_peak)
     mat, h = headline(args, A, k, q, s, torch, np)
@@ -625,12 +633,14 @@ def main():
     extras = {}
     var = {}
     basic = None
-    if not args.no_extras:
+    if want("passes"):
         for qq in PASS_SWEEP.get(args.workload, ()):
             t, _ = timed_runs(mat, k, qq, s, max(3, args.steps // 2), 1, torch)
             extras[f"ms_q{qq}"] = round(t, 3)
             log(f"q={qq}: {t:.3f} ms")
+    if want("variants"):
         var = variants(A, k, q, s, args.steps, torch, np, h["factors"][1])
+    if want("basic"):
         basic = basic_vs_fast(torch, np, mat, A)
     U, S, V = (t.detach() for t in h["factors"])
     S_host, V_host = S.cpu(), V.cpu()
@@ -638,10 +648,13 @@ def main():
     del U, S, V, h["factors"]
     free(torch)
     secondary = diff = eigs = planted = None
-    if not args.no_extras:
+    if want("zipf"):
         secondary = secondary_zipf(args, torch, np)
+    if want("planted"):
         planted = planted_cfg(args, torch, np)
+    if want("differentiated"):
         diff = differentiated(args, torch, np)
+    if want("eigsvds"):
         eigs = eigsvds_vs_fast(torch, np)
     cpu = None
     So = None
