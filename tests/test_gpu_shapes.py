@@ -29,6 +29,10 @@ def _cases():
         short = min(m, n)
         l = int(rng.integers(2, min(128, short) + 1))
         k = int(rng.integers(1, l + 1))
+        if i == 2:
+            l, k = 128, 100  # the widest sketch
+        if i == 5:
+            k = l            # no oversampling
         s = l - k
         q = 2 + i % 6
         density = min(0.2, 60_000 / (m * n) * 3)
