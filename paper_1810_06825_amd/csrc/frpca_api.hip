@@ -529,13 +529,15 @@ int frpca_create(frpca_t* out, int64_t m, int64_t n, int64_t nnz, const int64_t*
           h->bhotcol = static_cast<int32_t*>(h->alloc_owned(hh * sizeof(int32_t)));
           h->btailcol = static_cast<int32_t*>(h->alloc_owned(std::max<int64_t>(n - hh, 1) * sizeof(int32_t)));
           launch_colmap_inverse(h->colmap, n, h->bhotcol, h->btailcol, st);
-          uint32_t* bv = reinterpret_cast<uint32_t*>(h->bperm);
-          launch_bcsc_keys(static_cast<int32_t*>(row_of.p), col, nnz, h->colmap, hh, nblk, kk, st);
-          iota_kernel<<<(unsigned)((nnz + 255) / 256), 256, 0, st>>>(bv, nnz);
-          radix_sort_pairs(kk, bv, static_cast<uint32_t*>(keys_alt.p), static_cast<uint32_t*>(vals_alt.p), nnz,
-                           bits_for(nseg - 1), rtmp.p, st);
-          launch_ptr_from_sorted(kk, nnz, nseg, h->bptr, st);
-          launch_gather_csc(bv, static_cast<int32_t*>(row_of.p), val, nnz, h->brow, h->bval, st);
+          // the (row block, hot column) runs and the tail columns, read off the mirror
+          DeviceTemp rcnt((nseg + 1) * sizeof(int32_t)), rsrc(std::max<int64_t>(nseg, 1) * sizeof(int32_t)),
+              rscan(scan_temp_bytes(nseg));
+          int32_t* cnt = static_cast<int32_t*>(rcnt.p);
+          launch_bcsc_runs(h->cp32, h->row_csc, h->bhotcol, h->btailcol, hh, nblk, n - hh, kBcscRowShift, cnt,
+                           static_cast<int32_t*>(rsrc.p), st);
+          exclusive_scan_i32(cnt, h->bptr, nseg, rscan.p, st);
+          launch_bcsc_copy(h->bptr, static_cast<int32_t*>(rsrc.p), nseg, h->row_csc, h->val_csc, h->perm, h->brow,
+                           h->bval, h->bperm, st);
           check_launch();
           int32_t nnz_hot = 0;
           FRPCA_HIP(hipMemcpyAsync(&nnz_hot, h->bptr + nhs, sizeof(int32_t), hipMemcpyDeviceToHost, st));

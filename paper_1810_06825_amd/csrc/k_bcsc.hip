@@ -37,15 +37,6 @@ __global__ void colmap_kernel(const int32_t* hot, const int32_t* hpre, const int
   colmap[i] = hot[i] ? hpre[i] : -1 - tpre[i];
 }
 
-__global__ void keys_kernel(const int32_t* row_of, const int32_t* col, int64_t nnz, const int32_t* colmap,
-                            int64_t hot_cols, int64_t nblk, uint32_t* keys) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= nnz) return;
-  const int32_t cm = colmap[col[e]];
-  keys[e] = cm >= 0 ? (uint32_t)((int64_t)(row_of[e] >> kBcscRowShift) * hot_cols + cm)
-                    : (uint32_t)(nblk * hot_cols + (-1 - cm));
-}
-
 // Segment pointers of the tail part, rebased to its first nonzero.
 __global__ void rebase_kernel(const int32_t* ptr, int64_t count, int32_t base, int32_t* out) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -114,12 +105,6 @@ void launch_colmap(const int32_t* hot, const int32_t* hpre, const int32_t* tpre,
                    hipStream_t st) {
   if (n <= 0) return;
   colmap_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(hot, hpre, tpre, n, colmap);
-}
-
-void launch_bcsc_keys(const int32_t* row_of, const int32_t* col, int64_t nnz, const int32_t* colmap,
-                      int64_t hot_cols, int64_t nblk, uint32_t* keys, hipStream_t st) {
-  if (nnz <= 0) return;
-  keys_kernel<<<(unsigned)((nnz + 255) / 256), 256, 0, st>>>(row_of, col, nnz, colmap, hot_cols, nblk, keys);
 }
 
 void launch_rebase(const int32_t* ptr, int64_t count, int32_t base, int32_t* out, hipStream_t st) {

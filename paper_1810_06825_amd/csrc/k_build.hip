@@ -248,6 +248,60 @@ __global__ __launch_bounds__(256) void merge_fixplan_kernel(const int32_t* ptr, 
 
 inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
+// Row-blocked order of the transpose product, read off the column-major mirror (no second
+// sort): the rows of a column ascend in the mirror, so the nonzeros of hot column h inside row
+// block b are one contiguous run of that column, bounded by two binary searches. Segment
+// b * H + h gets that run; tail segment nhs + t gets the whole of tail column tailcol[t]. The
+// runs keep the mirror's order (rows ascending), the order a stable sort by (block, column)
+// of the row-major positions gives.
+__device__ __forceinline__ int32_t lower_row(const int32_t* rows, int32_t lo, int32_t hi, int64_t r) {
+  while (lo < hi) {
+    const int32_t mid = lo + ((hi - lo) >> 1);
+    if ((int64_t)rows[mid] < r) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void bcsc_hot_runs_kernel(const int32_t* cp, const int32_t* row_csc,
+                                                            const int32_t* hotcol, int64_t hh, int64_t nblk,
+                                                            int shift, int32_t* cnt, int32_t* src) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= nblk * hh) return;
+  const int64_t b = i / hh, h = i - b * hh;
+  const int32_t c = hotcol[h];
+  const int32_t lo = cp[c], hi = cp[c + 1];
+  const int32_t s0 = lower_row(row_csc, lo, hi, b << shift);
+  const int32_t s1 = lower_row(row_csc, s0, hi, (b + 1) << shift);
+  cnt[i] = s1 - s0;
+  src[i] = s0;
+}
+
+__global__ __launch_bounds__(256) void bcsc_tail_runs_kernel(const int32_t* cp, const int32_t* tailcol, int64_t ntail,
+                                                             int64_t nhs, int32_t* cnt, int32_t* src) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= ntail) return;
+  const int32_t c = tailcol[t];
+  cnt[nhs + t] = cp[c + 1] - cp[c];
+  src[nhs + t] = cp[c];
+}
+
+// A wave per segment copies its run of the mirror (rows, values, row-major positions).
+__global__ __launch_bounds__(256) void bcsc_copy_kernel(const int32_t* bptr, const int32_t* src, int64_t nseg,
+                                                        const int32_t* row_csc, const float* val_csc,
+                                                        const int32_t* perm, int32_t* brow, float* bval,
+                                                        int32_t* bperm) {
+  const int64_t seg = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (seg >= nseg) return;
+  const int lane = threadIdx.x & 63;
+  const int32_t d0 = bptr[seg], len = bptr[seg + 1] - d0, s0 = src[seg];
+  for (int32_t i = lane; i < len; i += 64) {
+    brow[d0 + i] = row_csc[s0 + i];
+    bval[d0 + i] = val_csc[s0 + i];
+    bperm[d0 + i] = perm[s0 + i];
+  }
+}
+
 }  // namespace
 
 void launch_validate_csr(int64_t m, int64_t n, int64_t nnz, const int64_t* row_ptr,
@@ -334,6 +388,21 @@ void launch_ptr_from_sorted(const uint32_t* keys, int64_t count, int64_t nseg, i
 void launch_gather_csc(const uint32_t* perm, const int32_t* row_of, const float* val, int64_t nnz,
                        int32_t* row_csc, float* val_csc, hipStream_t st) {
   if (nnz > 0) gather_csc_kernel<<<grid_for(nnz, 256), 256, 0, st>>>(perm, row_of, val, nnz, row_csc, val_csc);
+}
+
+void launch_bcsc_runs(const int32_t* cp, const int32_t* row_csc, const int32_t* hotcol, const int32_t* tailcol,
+                      int64_t hh, int64_t nblk, int64_t ntail, int shift, int32_t* cnt, int32_t* src, hipStream_t st) {
+  const int64_t nhs = nblk * hh;
+  if (nhs > 0)
+    bcsc_hot_runs_kernel<<<grid_for(nhs, 256), 256, 0, st>>>(cp, row_csc, hotcol, hh, nblk, shift, cnt, src);
+  if (ntail > 0) bcsc_tail_runs_kernel<<<grid_for(ntail, 256), 256, 0, st>>>(cp, tailcol, ntail, nhs, cnt, src);
+}
+
+void launch_bcsc_copy(const int32_t* bptr, const int32_t* src, int64_t nseg, const int32_t* row_csc,
+                      const float* val_csc, const int32_t* perm, int32_t* brow, float* bval, int32_t* bperm,
+                      hipStream_t st) {
+  if (nseg > 0)
+    bcsc_copy_kernel<<<grid_for(nseg, 4), 256, 0, st>>>(bptr, src, nseg, row_csc, val_csc, perm, brow, bval, bperm);
 }
 
 void launch_gather_values(const int32_t* perm, const float* val, int64_t nnz, float* out, hipStream_t st) {

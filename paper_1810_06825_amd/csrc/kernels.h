@@ -41,6 +41,16 @@ void launch_gather_csc(const uint32_t* perm, const int32_t* row_of, const float*
                        int64_t nnz, int32_t* row_csc, float* val_csc, hipStream_t st);
 void launch_gather_values(const int32_t* perm, const float* val, int64_t nnz, float* out,
                           hipStream_t st);
+// Row-blocked order from the column-major mirror (cp, row_csc with rows ascending per column):
+// cnt/src[b * hh + h] = length and mirror start of hot column hotcol[h]'s run in row block b
+// (blocks of 2^shift rows), cnt/src[nblk * hh + t] = the whole tail column tailcol[t]. After
+// an exclusive scan of cnt into bptr, launch_bcsc_copy moves each run (rows, values, row-major
+// positions perm) to bptr[seg].
+void launch_bcsc_runs(const int32_t* cp, const int32_t* row_csc, const int32_t* hotcol, const int32_t* tailcol,
+                      int64_t hh, int64_t nblk, int64_t ntail, int shift, int32_t* cnt, int32_t* src, hipStream_t st);
+void launch_bcsc_copy(const int32_t* bptr, const int32_t* src, int64_t nseg, const int32_t* row_csc,
+                      const float* val_csc, const int32_t* perm, int32_t* brow, float* bval, int32_t* bperm,
+                      hipStream_t st);
 
 // ---------------------------------------------------------------- blocked column order
 // (hot columns split by blocks of 2^kBcscRowShift rows; see k_bcsc.hip)
@@ -56,8 +66,6 @@ void launch_hot_flags(const int32_t* cp, int64_t n, int32_t thresh, int32_t* hot
 void launch_colmap(const int32_t* hot, const int32_t* hpre, const int32_t* tpre, int64_t n, int32_t* colmap,
                    hipStream_t st);
 // segments: nblk * hot_cols hot ones (row block major), then one per tail column
-void launch_bcsc_keys(const int32_t* row_of, const int32_t* col, int64_t nnz, const int32_t* colmap,
-                      int64_t hot_cols, int64_t nblk, uint32_t* keys, hipStream_t st);
 void launch_rebase(const int32_t* ptr, int64_t count, int32_t base, int32_t* out, hipStream_t st);
 // X[c] = sum over row blocks of the hot partial rows of c (fixed order), or the tail row of c.
 void launch_colmap_inverse(const int32_t* colmap, int64_t n, int32_t* hotcol, int32_t* tailcol, hipStream_t st);
