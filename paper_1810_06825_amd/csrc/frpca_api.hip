@@ -247,6 +247,7 @@ struct frpca_ctx {
     p.fix_w0 = static_cast<int32_t*>(alloc_owned(p.nwaves * sizeof(int32_t)));
     p.carry = static_cast<float*>(alloc_owned(p.nwaves * 128 * sizeof(float)));
     p.head = static_cast<float*>(alloc_owned(p.nwaves * 128 * sizeof(float)));
+    if (sweep) p.sweep_ctr = static_cast<int32_t*>(alloc_owned(8 * 32 * sizeof(int32_t)));
     launch_merge_partition(p, stream);
     launch_merge_fixplan(p, stream);
   }

@@ -13,8 +13,8 @@
 // A column is hot when it holds at least kHotPerBlock nonzeros per row block on average, so
 // every partial row amortizes its write over that many gathers. Segment order: the nblk x H
 // hot segments (row block major), then one segment per tail column. The two parts run as
-// separate merge-path launches: the hot one sweeps the row blocks in narrow rounds (each XCD
-// on its own stretch) so its gathers hit L2, and the tail's random-row gathers, which would
+// separate merge-path launches: the hot one sweeps the row blocks in order, each XCD taking
+// its own chunks of partitions one after another from a counter, so its gathers hit L2, and the tail's random-row gathers, which would
 // evict those blocks, come afterwards and write their rows of the result directly (the plan
 // maps tail segment i to column tailcol[i]).
 #include "kernels.h"

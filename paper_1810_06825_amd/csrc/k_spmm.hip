@@ -37,21 +37,42 @@ struct SpmmArgs {
   const int32_t* out_row;  // output row of each segment (identity when null)
   const float* csub_v;     // rank-1 term out[r] -= csub_s[r] * csub_v (none when null)
   const float* csub_s;     //   (factor 1 when null)
+  int32_t* sweep_ctr;      // sweep mode: per-XCD partition tickets (zeroed before each launch)
 };
 
-// Sweep mode: a grid of resident waves walks the partitions in rounds (round i covers
-// partitions [i G, (i+1) G) for G resident waves), and within a round the blocks that the
-// hardware places on one XCD (round-robin by block index) take one contiguous stretch. The
-// partitions in flight then cover a narrow band of the segment order, which the row-blocked
-// transpose product needs for its gathered panel rows to stay in each XCD's L2.
-#ifndef FRPCA_SWEEP_XCD
-#define FRPCA_SWEEP_XCD 1
+// Sweep mode: a grid of resident waves takes the partitions from counters. The partitions are
+// dealt to the XCDs in chunks of kSweepChunk consecutive ones (chunk j to XCD j mod 8, by the
+// hardware's round-robin placement of blocks on XCDs), and the waves of an XCD take its
+// partitions in order, each wave its next one from the XCD's counter when it finishes the last.
+// The partitions in flight on an XCD then stay within about one chunk of the segment order,
+// which the row-blocked transpose product needs for its gathered panel rows to stay in that
+// XCD's L2. (Walking fixed rounds instead let the waves drift apart over the rounds and widened
+// the band: the hot part of the 12.9M-row transpose product took 6.2 ms against 4.2.)
+#ifndef FRPCA_SWEEP_CHUNK
+#define FRPCA_SWEEP_CHUNK 512
 #endif
-__device__ __forceinline__ int64_t sweep_block(int64_t round) {
-  const int64_t g = gridDim.x, q = g / 8, r = g % 8, b = blockIdx.x, x = b % 8;
-  if (!FRPCA_SWEEP_XCD) return round * g + b;
-  return round * g + x * q + min(x, r) + b / 8;
+constexpr int kSweepChunk = FRPCA_SWEEP_CHUNK;
+
+template <class F>
+__device__ __forceinline__ void sweep_partitions(const SpmmArgs& a, int lane, F&& run) {
+  const int nx = min((int)gridDim.x, 8);  // virtual XCDs, each with at least one block
+  const int x = blockIdx.x % nx;
+  int* ctr = a.sweep_ctr + 32 * x;  // one counter per 128-byte line
+  int t = 0;
+  if (lane == 0) t = atomicAdd(ctr, 1);
+  int k = __builtin_amdgcn_readlane(t, 0);
+  for (;;) {
+    // the XCD's k-th partition: tickets are handed out in increasing order and this map is
+    // increasing in k, so once a ticket lies past the end every later one does too
+    const int64_t w = ((int64_t)(k / kSweepChunk) * nx + x) * kSweepChunk + k % kSweepChunk;
+    if (w >= a.nwaves) break;
+    if (lane == 0) t = atomicAdd(ctr, 1);  // the next ticket, taken before this partition's work
+    run(w);
+    k = __builtin_amdgcn_readlane(t, 0);
+  }
 }
+
+__global__ void sweep_reset_kernel(int32_t* ctr) { ctr[threadIdx.x] = 0; }
 
 constexpr int kBatch = 8;  // gathers in flight per wave
 #ifndef FRPCA_SWEEP_BLOCKS
@@ -208,11 +229,7 @@ __global__ __launch_bounds__(256) void spmm_merge_kernel(SpmmArgs a) {
     if (w < a.nwaves) spmm_partition<IN_BF16>(a, w, lane, lw);
     return;
   }
-  for (int64_t round = 0;; ++round) {
-    const int64_t w = sweep_block(round) * 4 + wv;
-    if (w >= a.nwaves) break;
-    spmm_partition<IN_BF16>(a, w, lane, lw);
-  }
+  sweep_partitions(a, lane, [&](int64_t w) { spmm_partition<IN_BF16>(a, w, lane, lw); });
 }
 
 // ---------------------------------------------------------------------------------------
@@ -421,11 +438,7 @@ __global__ __launch_bounds__(256, FRPCA_SPMM_MINW) void spmm_merge4_kernel(SpmmA
     if (w < a.nwaves) spmm_partition4<IN_BF16, NT>(a, w, lane, lw);
     return;
   }
-  for (int64_t round = 0;; ++round) {
-    const int64_t w = sweep_block(round) * 4 + wv;
-    if (w >= a.nwaves) break;
-    spmm_partition4<IN_BF16, NT>(a, w, lane, lw);
-  }
+  sweep_partitions(a, lane, [&](int64_t w) { spmm_partition4<IN_BF16, NT>(a, w, lane, lw); });
 }
 
 // out[c] = carry[w0] + ... + carry[w1-1] + head[w1] for segments cut by partition bounds
@@ -487,7 +500,8 @@ void launch_spmm_main(const MergePlan& p, int lp, const void* in, bool in_bf16, 
                       uint16_t* out_bf16, int ld_out, hipStream_t st, SpmmCorr corr) {
   if (p.nwaves <= 0) return;
   SpmmArgs a{p.ptr, p.idx, p.val, p.part_seg, p.part_e, p.nseg, p.nwaves, in, ld_in, out_f32, out_bf16,
-             ld_out, lp, p.carry, p.head, p.sweep, p.out_row, corr.v, corr.s};
+             ld_out, lp, p.carry, p.head, p.sweep, p.out_row, corr.v, corr.s, p.sweep_ctr};
+  if (p.sweep) sweep_reset_kernel<<<1, 256, 0, st>>>(p.sweep_ctr);  // a kernel, not a memset: capturable
   unsigned grid = (unsigned)((p.nwaves + 3) / 4);
   if (p.sweep && grid > kSweepBlocks) grid = kSweepBlocks;
   // paired 16-byte gathers when every row of in and out starts 16-byte (FP32) or 8-byte

@@ -59,7 +59,7 @@ void launch_bcsc_copy(const int32_t* bptr, const int32_t* src, int64_t nseg, con
 #endif
 constexpr int kBcscRowShift = FRPCA_BCSC_ROW_SHIFT;
 #ifndef FRPCA_HOT_PER_BLOCK
-#define FRPCA_HOT_PER_BLOCK 12
+#define FRPCA_HOT_PER_BLOCK 6
 #endif
 constexpr int kHotPerBlock = FRPCA_HOT_PER_BLOCK;
 void launch_hot_flags(const int32_t* cp, int64_t n, int32_t thresh, int32_t* hot, int32_t* tail, hipStream_t st);
@@ -97,6 +97,7 @@ struct MergePlan {
   const int32_t* out_row = nullptr;  // [nseg] output row of each segment (identity when null)
   float* carry = nullptr;         // [nwaves*128] partial sums carried out of each wave
   float* head = nullptr;          // [nwaves*128] partial sums of continued first segments
+  int32_t* sweep_ctr = nullptr;   // sweep mode: per-XCD partition counters (8 x 32 ints)
   int64_t in_rows = 0;            // rows of the gathered panel (0: unknown)
 };
 // Gathered panels larger than this are read with streaming (non-temporal) loads: 8 times the

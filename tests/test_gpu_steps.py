@@ -127,11 +127,14 @@ def test_spmm_width_not_multiple_of_4(trans):
     assert np.all(np.abs(got - ref) <= 1e-5 * bound + 1e-30)
 
 
-@pytest.mark.parametrize("layout", ["all_hot", "no_hot", "mixed"])
+@pytest.mark.parametrize("layout", ["all_hot", "no_hot", "mixed", "tiny_hot"])
 def test_transpose_product_layouts(layout):
     """A^T Y through the row-blocked order when every column is frequent (no tail part), when
-    none is (plain column order), and for a mix over several row blocks; exact on integers."""
-    if layout == "all_hot":
+    none is (plain column order), for a mix over several row blocks, and for a hot part of a
+    dozen partitions (a sweep grid of fewer blocks than XCDs); exact on integers."""
+    if layout == "tiny_hot":
+        A = random_sparse(300, 4, 0.9, seed=24, integer_values=True)
+    elif layout == "all_hot":
         A = random_sparse(3000, 50, 0.3, seed=21, integer_values=True)
     elif layout == "no_hot":
         A = random_sparse(20_000, 20_000, 1e-4, seed=22, integer_values=True)
@@ -141,7 +144,7 @@ def test_transpose_product_layouts(layout):
     say("transpose layout", layout, A.m, A.n, A.nnz)
     mat = _mat(A)
     info = mat.info()
-    if layout == "all_hot":
+    if layout in ("all_hot", "tiny_hot"):
         assert info["hot_cols"] == A.n and info["hot_nnz"] == A.nnz
     elif layout == "no_hot":
         assert info["hot_cols"] == 0
