@@ -76,16 +76,19 @@ def _spmm(mat, trans, X, ld, in_bf16=False, out_bf16=False):
 
 
 @pytest.mark.parametrize("trans", [0, 1])
-def test_spmm_integer_values_bit_exact(trans):
+@pytest.mark.parametrize("ld", [64, 128])
+def test_spmm_integer_values_bit_exact(trans, ld):
+    # ld 64: one column half; ld 128: the halves on separate XCD groups
     A = random_sparse(2500, 1700, 0.01, seed=11, empty_rows=(3, 2499), empty_cols=(0, 5), integer_values=True)
     rows_in = A.m if trans else A.n
-    X = np.random.default_rng(2).integers(-8, 9, size=(rows_in, 60)).astype(np.float64)
-    say("spmm integer", trans, A.m, A.n, A.nnz)
+    l = ld - 4
+    X = np.random.default_rng(2).integers(-8, 9, size=(rows_in, l)).astype(np.float64)
+    say("spmm integer", trans, ld, A.m, A.n, A.nnz)
     mat = _mat(A)
-    got = _spmm(mat, trans, X, 64)
+    got = _spmm(mat, trans, X, ld)
     ref = oracle.csr_tmatmul(A, X) if trans else oracle.csr_matmul(A, X)
-    assert np.array_equal(got[:, :60], ref)
-    assert np.all(got[:, 60:] == 0)
+    assert np.array_equal(got[:, :l], ref)
+    assert np.all(got[:, l:] == 0)
 
 
 @pytest.mark.parametrize("trans", [0, 1])
