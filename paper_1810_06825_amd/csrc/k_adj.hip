@@ -82,6 +82,9 @@ __global__ __launch_bounds__(256) void sddmm_kernel(const int32_t* rp, const int
 // are gathered before any is reduced, and each half-wave sum runs on DPP row shifts (lanes 31
 // and 63 end with the totals), so no LDS shuffles are needed.
 constexpr int kSdPairs = 8;
+#ifndef FRPCA_SDDMM_QUAD
+#define FRPCA_SDDMM_QUAD 1
+#endif
 
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ float dppf(float v) {
@@ -99,15 +102,28 @@ __device__ __forceinline__ float half_sum_last(float v) {
   return v;
 }
 
+// Sum over each row of 16 lanes, valid in its lane 15.
+__device__ __forceinline__ float row_sum_last(float v) {
+  v += dppf<0x111, 0xF>(v);
+  v += dppf<0x112, 0xF>(v);
+  v += dppf<0x114, 0xF>(v);
+  v += dppf<0x118, 0xF>(v);
+  return v;
+}
+
 // TWO: the second product term is present; CORR: the per-column centring term is present. Both
 // are compile-time so the kSdPairs gathers of a batch issue back to back before any arithmetic
-// (a run-time test between them makes the compiler wait for each gather in turn).
-template <bool TWO, bool CORR>
+// (a run-time test between them makes the compiler wait for each gather in turn). G: nonzeros
+// per gather instruction, 2 (half-waves of 32 lanes, panels up to 128 columns) or 4 (rows of
+// 16 lanes, panels up to 64 columns, whose pairs would leave half of each half-wave idle).
+template <bool TWO, bool CORR, int G>
 __global__ __launch_bounds__(256) void sddmm4_kernel(const int32_t* rp, const int32_t* col, int64_t m, int w,
                                                      const float* P1, const float* Q1, const float* P2,
                                                      const float* Q2, const float* corr, float* dval) {
-  const int lane = threadIdx.x & 63, half = lane >> 5;
-  const int c4 = 4 * (lane & 31);
+  static_assert(G == 2 || G == 4, "two or four nonzeros per gather");
+  constexpr int kLanes = 64 / G;  // lanes per nonzero
+  const int lane = threadIdx.x & 63, half = lane / kLanes;
+  const int c4 = 4 * (lane % kLanes);
   const bool act = c4 < w;
   const int gc = act ? c4 : 0;
   const int64_t wave0 = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -149,20 +165,26 @@ __global__ __launch_bounds__(256) void sddmm4_kernel(const int32_t* rp, const in
     // the index is 0, a valid column whose result is discarded
     auto chunk = [&](int ec, int ci) {
       const int nb = __builtin_amdgcn_readfirstlane(min(64, e1 - ec));
-      for (int b = 0; b < nb; b += 2 * kSdPairs) {
+      for (int b = 0; b < nb; b += G * kSdPairs) {
         const int e = ec + b;
         int cs[kSdPairs];
         float4 q[kSdPairs], q2[kSdPairs];
         float cv[kSdPairs];
 #pragma unroll
         for (int p = 0; p < kSdPairs; ++p) {
-          const int ce = __builtin_amdgcn_readlane(ci, (b + 2 * p) & 63);
-          const int co = __builtin_amdgcn_readlane(ci, (b + 2 * p + 1) & 63);
-          cs[p] = half ? co : ce;
+          const int ce = __builtin_amdgcn_readlane(ci, (b + G * p) & 63);
+          const int co = __builtin_amdgcn_readlane(ci, (b + G * p + 1) & 63);
+          if constexpr (G == 2) {
+            cs[p] = half ? co : ce;
+          } else {
+            const int c2 = __builtin_amdgcn_readlane(ci, (b + G * p + 2) & 63);
+            const int c3 = __builtin_amdgcn_readlane(ci, (b + G * p + 3) & 63);
+            cs[p] = half == 0 ? ce : half == 1 ? co : half == 2 ? c2 : c3;
+          }
           q[p] = q2[p] = make_float4(0.f, 0.f, 0.f, 0.f);
           cv[p] = 0.f;
-          // pairs past the chunk's end are not gathered (the test is uniform over the wave)
-          if (b + 2 * p < nb) {
+          // groups past the chunk's end are not gathered (the test is uniform over the wave)
+          if (b + G * p < nb) {
             q[p] = *reinterpret_cast<const float4*>(Q1 + (size_t)cs[p] * w + gc);
             if (TWO) q2[p] = *reinterpret_cast<const float4*>(Q2 + (size_t)cs[p] * w + gc);
             if (CORR) cv[p] = corr[cs[p]];
@@ -172,9 +194,9 @@ __global__ __launch_bounds__(256) void sddmm4_kernel(const int32_t* rp, const in
         for (int p = 0; p < kSdPairs; ++p) {
           float s = x.x * q[p].x + x.y * q[p].y + x.z * q[p].z + x.w * q[p].w;
           if (TWO) s += y.x * q2[p].x + y.y * q2[p].y + y.z * q2[p].z + y.w * q2[p].w;
-          const float t = half_sum_last(act ? s : 0.f);
-          const int ee = e + 2 * p + half;
-          if ((lane & 31) == 31 && ee < e1) dval[ee] = CORR ? t - cv[p] : t;
+          const float t = G == 2 ? half_sum_last(act ? s : 0.f) : row_sum_last(act ? s : 0.f);
+          const int ee = e + G * p + half;
+          if (lane % kLanes == kLanes - 1 && ee < e1) dval[ee] = CORR ? t - cv[p] : t;
         }
       }
     };
@@ -210,10 +232,15 @@ void launch_sddmm(const int32_t* rp, const int32_t* col, int64_t m, int w, const
   auto al = [](const float* p) { return p == nullptr || (reinterpret_cast<uintptr_t>(p) % 16) == 0; };
   if (w % 4 == 0 && w <= 128 && al(P1) && al(Q1) && al(P2) && al(Q2)) {
     const bool two = P2 != nullptr && Q2 != nullptr;
-    if (two && corr) sddmm4_kernel<true, true><<<(unsigned)grid, 256, 0, st>>>(rp, col, m, w, P1, Q1, P2, Q2, corr, dval);
-    else if (two) sddmm4_kernel<true, false><<<(unsigned)grid, 256, 0, st>>>(rp, col, m, w, P1, Q1, P2, Q2, corr, dval);
-    else if (corr) sddmm4_kernel<false, true><<<(unsigned)grid, 256, 0, st>>>(rp, col, m, w, P1, Q1, P2, Q2, corr, dval);
-    else sddmm4_kernel<false, false><<<(unsigned)grid, 256, 0, st>>>(rp, col, m, w, P1, Q1, P2, Q2, corr, dval);
+    auto go = [&](auto g) {
+      constexpr int G = decltype(g)::value;
+      if (two && corr) sddmm4_kernel<true, true, G><<<(unsigned)grid, 256, 0, st>>>(rp, col, m, w, P1, Q1, P2, Q2, corr, dval);
+      else if (two) sddmm4_kernel<true, false, G><<<(unsigned)grid, 256, 0, st>>>(rp, col, m, w, P1, Q1, P2, Q2, corr, dval);
+      else if (corr) sddmm4_kernel<false, true, G><<<(unsigned)grid, 256, 0, st>>>(rp, col, m, w, P1, Q1, P2, Q2, corr, dval);
+      else sddmm4_kernel<false, false, G><<<(unsigned)grid, 256, 0, st>>>(rp, col, m, w, P1, Q1, P2, Q2, corr, dval);
+    };
+    if (w <= 64 && FRPCA_SDDMM_QUAD) go(std::integral_constant<int, 4>{});
+    else go(std::integral_constant<int, 2>{});
     return;
   }
   sddmm_kernel<<<(unsigned)grid, 256, 0, st>>>(rp, col, m, w, P1, Q1, P2, Q2, corr, dval);

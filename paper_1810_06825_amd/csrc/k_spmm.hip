@@ -424,6 +424,9 @@ __device__ __forceinline__ void spmm_partition4(const SpmmArgs& a, int64_t w, in
   }
 }
 
+#ifndef FRPCA_SPMM_QUAD
+#define FRPCA_SPMM_QUAD 1
+#endif
 #ifndef FRPCA_SPMM_MINW
 #define FRPCA_SPMM_MINW 1
 #endif
@@ -439,6 +442,176 @@ __global__ __launch_bounds__(256, FRPCA_SPMM_MINW) void spmm_merge4_kernel(SpmmA
     return;
   }
   sweep_partitions(a, lane, [&](int64_t w) { spmm_partition4<IN_BF16, NT>(a, w, lane, lw); });
+}
+
+// ---------------------------------------------------------------------------------------
+// Quad gathers, for panels of at most 64 computed columns (where the paired kernel would
+// leave half of each half-wave idle): the lanes of quarter q (lane / 16) take entry 4i + q of
+// each quad of nonzeros, sixteen lanes covering 64 columns at four per lane, so one
+// vector-memory instruction still fetches four rows. The quarters meet through two
+// cross-quarter shuffles at each segment end; a segment ending inside a quad takes the
+// quarters before its end.
+constexpr int kQuads = 4;  // quads per batch; two batches in flight
+
+template <bool IN_BF16, bool NT>
+__device__ __forceinline__ void spmm_partition_q(const SpmmArgs& a, int64_t w, int lane, int* lw) {
+  const int quarter = lane >> 4;
+  const int col = 4 * (lane & 15);
+  const bool act = col < a.lp;
+  const int gcol = act ? col : 0;
+  int seg = a.part_seg[w];
+  const int seg_stop = a.part_seg[w + 1];
+  int e = a.part_e[w];
+  const int e_stop = a.part_e[w + 1];
+  bool pending_head = (seg < a.nseg) && (a.ptr[seg] < e);
+  int pbase = seg;
+  auto refill = [&]() {
+    lw[lane] = (pbase + 1 + lane <= a.nseg) ? a.ptr[pbase + 1 + lane] : INT_MAX;
+    if (a.out_row) lw[64 + lane] = (pbase + lane < a.nseg) ? a.out_row[pbase + lane] : 0;
+  };
+  refill();
+  int next_end = (seg < seg_stop) ? __builtin_amdgcn_readfirstlane(lw[0]) : INT_MAX;
+  float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+
+  auto quad_sum = [&]() {
+    float4 t;
+    t.x = acc.x + __shfl_xor(acc.x, 16);
+    t.y = acc.y + __shfl_xor(acc.y, 16);
+    t.z = acc.z + __shfl_xor(acc.z, 16);
+    t.w = acc.w + __shfl_xor(acc.w, 16);
+    t.x += __shfl_xor(t.x, 32);
+    t.y += __shfl_xor(t.y, 32);
+    t.z += __shfl_xor(t.z, 32);
+    t.w += __shfl_xor(t.w, 32);
+    return t;
+  };
+  auto emit = [&]() {
+    float4 t = quad_sum();
+    if (quarter == 0 && act) {
+      if (pending_head) {
+        *reinterpret_cast<float4*>(a.head + (size_t)w * 128 + col) = t;
+      } else {
+        const int64_t orow = a.out_row ? lw[64 + seg - pbase] : seg;
+        if (a.csub_v) {
+          const float sc = a.csub_s ? a.csub_s[orow] : 1.f;
+          const float4 cv = *reinterpret_cast<const float4*>(a.csub_v + col);
+          t.x -= sc * cv.x;
+          t.y -= sc * cv.y;
+          t.z -= sc * cv.z;
+          t.w -= sc * cv.w;
+        }
+        const size_t o = (size_t)orow * a.ld_out + col;
+        typedef float v4f __attribute__((ext_vector_type(4)));
+        if (a.out_f32) {
+          const v4f tv = {t.x, t.y, t.z, t.w};
+          __builtin_nontemporal_store(tv, reinterpret_cast<v4f*>(a.out_f32 + o));
+        }
+        if (a.out_bf16) {
+          uint2 b;
+          b.x = (uint32_t)f32_to_bf16(t.x) | ((uint32_t)f32_to_bf16(t.y) << 16);
+          b.y = (uint32_t)f32_to_bf16(t.z) | ((uint32_t)f32_to_bf16(t.w) << 16);
+          *reinterpret_cast<uint2*>(a.out_bf16 + o) = b;
+        }
+      }
+    }
+    pending_head = false;
+    acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    ++seg;
+    if (seg < seg_stop) {
+      if (seg - pbase >= 64) {
+        pbase += 64;
+        refill();
+      }
+      next_end = __builtin_amdgcn_readfirstlane(lw[seg - pbase]);
+    } else {
+      next_end = INT_MAX;
+    }
+  };
+
+  int wbase = e;
+  int widx = 0, nidx = 0;
+  float wval = 0.f, nval = 0.f;
+  if (wbase + lane < e_stop) {
+    widx = stream_load(a.idx + wbase + lane);
+    wval = stream_load(a.val + wbase + lane);
+  }
+  float pv[kQuads];
+  float4 px[kQuads];
+  int pe = 0, pend = 0;  // pending batch: entries [pe, pend)
+  auto consume = [&]() {
+#pragma unroll
+    for (int p = 0; p < kQuads; ++p) {
+      const int eq = pe + 4 * p;
+      if (eq < pend) {
+        while (next_end <= eq) emit();
+        // quarters lo.. of the quad are still to be added; a segment that ends after entry
+        // next_end - 1 inside the quad takes the quarters before its end
+        int lo = 0;
+        while (next_end < eq + 4 && next_end < pend) {
+          const int hi = next_end - eq;
+          fma4(acc, (quarter >= lo && quarter < hi) ? pv[p] : 0.f, px[p]);
+          lo = hi;
+          while (next_end <= eq + lo) emit();
+        }
+        fma4(acc, quarter >= lo ? pv[p] : 0.f, px[p]);
+      }
+    }
+  };
+  while (e < e_stop) {
+    const int wend = min(wbase + 64, e_stop);
+    if (wbase + 64 + lane < e_stop) {
+      nidx = stream_load(a.idx + wbase + 64 + lane);
+      nval = stream_load(a.val + wbase + 64 + lane);
+    }
+    while (e < wend) {
+      const int stop = min(e + 4 * kQuads, wend);
+      const int off = e - wbase;
+      float v[kQuads];
+      float4 x[kQuads];
+#pragma unroll
+      for (int p = 0; p < kQuads; ++p) {
+        // this quarter's entry of quad p (entries past the batch gather row 0 with weight 0)
+        const int src = off + 4 * p + quarter;
+        const bool valid = e + 4 * p + quarter < stop;
+        const int c = __shfl(widx, src & 63);
+        const float vv = __shfl(wval, src & 63);
+        v[p] = valid ? vv : 0.f;
+        x[p] = load4<IN_BF16, NT>(a.in, (size_t)(valid ? c : 0) * a.ld_in + gcol);
+      }
+      consume();
+#pragma unroll
+      for (int p = 0; p < kQuads; ++p) {
+        pv[p] = v[p];
+        px[p] = x[p];
+      }
+      pe = e;
+      pend = stop;
+      e = stop;
+    }
+    wbase += 64;
+    widx = nidx;
+    wval = nval;
+  }
+  consume();
+  while (seg < seg_stop) emit();
+  if (seg_stop < a.nseg) {
+    const float4 t = quad_sum();
+    if (quarter == 0 && act) *reinterpret_cast<float4*>(a.carry + (size_t)w * 128 + col) = t;
+  }
+}
+
+template <bool IN_BF16, bool NT>
+__global__ __launch_bounds__(256, FRPCA_SPMM_MINW) void spmm_quad_kernel(SpmmArgs a) {
+  __shared__ int win[4][128];  // per wave: 64 segment ends, then 64 output rows
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  int* lw = win[wv];
+  if (!a.sweep) {
+    const int64_t w = (int64_t)blockIdx.x * 4 + wv;
+    if (w < a.nwaves) spmm_partition_q<IN_BF16, NT>(a, w, lane, lw);
+    return;
+  }
+  sweep_partitions(a, lane, [&](int64_t w) { spmm_partition_q<IN_BF16, NT>(a, w, lane, lw); });
 }
 
 // out[c] = carry[w0] + ... + carry[w1-1] + head[w1] for segments cut by partition bounds
@@ -514,6 +687,16 @@ void launch_spmm_main(const MergePlan& p, int lp, const void* in, bool in_bf16, 
     // streaming gathers for a panel many times the Infinity Cache (not in sweep mode, whose
     // gathered rows are meant to stay in L2)
     const bool nt = !p.sweep && p.in_rows > 0 && (double)p.in_rows * ld_in * ein > kStreamPanelBytes;
+    if (lp <= 64 && FRPCA_SPMM_QUAD) {
+      if (in_bf16) {
+        if (nt) spmm_quad_kernel<true, true><<<grid, 256, 0, st>>>(a);
+        else spmm_quad_kernel<true, false><<<grid, 256, 0, st>>>(a);
+      } else {
+        if (nt) spmm_quad_kernel<false, true><<<grid, 256, 0, st>>>(a);
+        else spmm_quad_kernel<false, false><<<grid, 256, 0, st>>>(a);
+      }
+      return;
+    }
     if (in_bf16) {
       if (nt) spmm_merge4_kernel<true, true><<<grid, 256, 0, st>>>(a);
       else spmm_merge4_kernel<true, false><<<grid, 256, 0, st>>>(a);

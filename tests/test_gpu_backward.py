@@ -21,8 +21,9 @@ def _rows(A):
 
 @pytest.mark.parametrize("k,t", [(25, 30), (24, 31), (100, 40)])
 def test_backward_matches_fp64_formula_at_gpu_factors(k, t):
-    # k = 24 runs the paired 16-byte SDDMM (odd row lengths leave a single last entry);
-    # k = 25 the two-column-per-lane form; k = 100 the cross-Gram with seven 16-column tiles
+    # k = 24 runs the SDDMM with four nonzeros per 16-byte gather (rows ending inside a group
+    # of four); k = 25 the two-column-per-lane form; k = 100 the paired SDDMM and the
+    # cross-Gram with seven 16-column tiles
     # (a pair and a single tile after the group of four) and the 112-deep panel product
     A = zipf_normal(m=20_000, n=4_000, t=t)
     q, s = 4, 10
