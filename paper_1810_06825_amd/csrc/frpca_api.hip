@@ -549,7 +549,7 @@ int frpca_create(frpca_t* out, int64_t m, int64_t n, int64_t nnz, const int64_t*
           // XCD, each on one partition) covers about two row blocks per XCD, whose rows of Y
           // (2 MB each at l = 128) then stay in that XCD's 4 MB L2
           const int64_t sweep_ipw =
-              std::max<int64_t>(kSweepMinIpw, std::min<int64_t>(kSweepItemsPerWave, nnz_hot / nblk / 256));
+              std::max<int64_t>(kSweepMinIpw, std::min<int64_t>(kSweepItemsPerWave, nnz_hot / nblk / FRPCA_SWEEP_PARTS));
           h->build_plan(h->bhotp, h->bptr, h->brow, h->bval, nhs, true, nnz_hot, sweep_ipw);
           h->build_plan(h->btailp, h->bptr_tail, h->brow + nnz_hot, h->bval + nnz_hot, n - hh, false,
                         nnz - nnz_hot);

@@ -110,6 +110,9 @@ int64_t merge_items_per_wave(int64_t nseg, int64_t nnz);
 #define FRPCA_SWEEP_IPW 384
 #endif
 constexpr int64_t kSweepItemsPerWave = FRPCA_SWEEP_IPW;  // largest partition of sweep-mode plans
+#ifndef FRPCA_SWEEP_PARTS
+#define FRPCA_SWEEP_PARTS 256  // sweep partitions per row block (before the ipw clamps)
+#endif
 #ifndef FRPCA_SWEEP_MIN_IPW
 #define FRPCA_SWEEP_MIN_IPW 96
 #endif
