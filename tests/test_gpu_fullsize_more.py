@@ -3,7 +3,8 @@ bench.py (panels with leading dimension 128, k = 100, s = 20):
 
 * aminer_tfidf, 12,869,521 x 323,899 (257,390,420 nnz, Zipf 1.0 columns, tf-idf values),
   q = 5: sampled rows of A Q and sampled columns of A^T Y (the hottest column, about
-  10M terms, among them) against FP64 sums of the same FP32 inputs; sampled rows of
+  10M terms, among them) against FP64 sums of the same FP32 inputs, on 128- and 64-column
+  panels; sampled rows of
   A V = U diag(S) in FP64; and the whole method at q = 3, 5 and 7 against the oracle on the
   whole matrix. Properties that hold at any size: orthonormal U and V, descending S, the sign
   convention, repeatability.
@@ -69,11 +70,15 @@ def aminer():
     mat.close()
 
 
-def test_aminer_products_sampled(aminer):
+@pytest.mark.parametrize("L,LD", [(L, LD), (60, 64)])
+def test_aminer_products_sampled(aminer, L, LD):
+    # 64-column panels run the four-nonzeros-per-gather kernels in all three modes: the
+    # forward product, the row-blocked hot part (sweep) and the tail part, whose 3.3 GB
+    # gathered panel takes streaming loads
     A, mat = aminer
     rng = np.random.default_rng(11)
     Acsr = sp.csr_matrix((A.val.astype(np.float64), A.col, A.row_ptr), shape=(A.m, A.n))
-    say("aminer Omega + A Q", A.n, L)
+    say("aminer Omega + A Q", A.n, L, LD)
     Om = torch.zeros((A.n, LD), dtype=torch.float32, device=DEV)
     binding.frpca_gaussian(mat.h, SEED, A.n, L, LD, Om)
     Q64 = Om[:, :L].double().cpu().numpy()
