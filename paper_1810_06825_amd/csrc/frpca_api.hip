@@ -98,7 +98,7 @@ struct frpca_ctx {
   // column is hot
   bool has_bcsc = false;
   MergePlan bhotp, btailp;  // hot segments (sweep mode) and tail columns
-  int32_t *bptr = nullptr, *bptr_tail = nullptr, *brow = nullptr, *bperm = nullptr, *colmap = nullptr;
+  int32_t *bptr = nullptr, *bptr_tail = nullptr, *brow = nullptr, *bsrc = nullptr, *colmap = nullptr;
   int32_t *bhotcol = nullptr, *btailcol = nullptr;  // hot / tail index -> column
   // centred products (opts.center): column means of A, and the rank-1 term's vector with its
   // reduction partials (k_center.hip)
@@ -523,7 +523,6 @@ int frpca_create(frpca_t* out, int64_t m, int64_t n, int64_t nnz, const int64_t*
           h->colmap = static_cast<int32_t*>(h->alloc_owned(n * sizeof(int32_t)));
           h->bptr = static_cast<int32_t*>(h->alloc_owned((nseg + 1) * sizeof(int32_t)));
           h->brow = static_cast<int32_t*>(h->alloc_owned(nnz * sizeof(int32_t)));
-          h->bperm = static_cast<int32_t*>(h->alloc_owned(nnz * sizeof(int32_t)));
           h->bval = static_cast<float*>(h->alloc_owned(nnz * sizeof(float)));
           launch_colmap(static_cast<int32_t*>(hot.p), static_cast<int32_t*>(hpre.p), static_cast<int32_t*>(tpre.p),
                         n, h->colmap, st);
@@ -531,14 +530,14 @@ int frpca_create(frpca_t* out, int64_t m, int64_t n, int64_t nnz, const int64_t*
           h->btailcol = static_cast<int32_t*>(h->alloc_owned(std::max<int64_t>(n - hh, 1) * sizeof(int32_t)));
           launch_colmap_inverse(h->colmap, n, h->bhotcol, h->btailcol, st);
           // the (row block, hot column) runs and the tail columns, read off the mirror
-          DeviceTemp rcnt((nseg + 1) * sizeof(int32_t)), rsrc(std::max<int64_t>(nseg, 1) * sizeof(int32_t)),
-              rscan(scan_temp_bytes(nseg));
+          // (the runs' mirror starts are kept: new values reach the blocked order by the same copies)
+          DeviceTemp rcnt((nseg + 1) * sizeof(int32_t)), rscan(scan_temp_bytes(nseg));
+          h->bsrc = static_cast<int32_t*>(h->alloc_owned(std::max<int64_t>(nseg, 1) * sizeof(int32_t)));
           int32_t* cnt = static_cast<int32_t*>(rcnt.p);
           launch_bcsc_runs(h->cp32, h->row_csc, h->bhotcol, h->btailcol, hh, nblk, n - hh, kBcscRowShift, cnt,
-                           static_cast<int32_t*>(rsrc.p), st);
+                           h->bsrc, st);
           exclusive_scan_i32(cnt, h->bptr, nseg, rscan.p, st);
-          launch_bcsc_copy(h->bptr, static_cast<int32_t*>(rsrc.p), nseg, h->row_csc, h->val_csc, h->perm, h->brow,
-                           h->bval, h->bperm, st);
+          launch_bcsc_copy(h->bptr, h->bsrc, nseg, h->row_csc, h->val_csc, h->brow, h->bval, st);
           check_launch();
           int32_t nnz_hot = 0;
           FRPCA_HIP(hipMemcpyAsync(&nnz_hot, h->bptr + nhs, sizeof(int32_t), hipMemcpyDeviceToHost, st));
@@ -586,7 +585,7 @@ int frpca_set_values(frpca_t h, const float* val) {
     h->csr.val = val;
     h->saved_k = 0;  // the last run's factors belong to the old values
     launch_gather_values(h->perm, val, h->nnz, h->val_csc, h->stream);
-    if (h->has_bcsc) launch_gather_values(h->bperm, val, h->nnz, h->bval, h->stream);
+    if (h->has_bcsc) launch_bcsc_values(h->bptr, h->bsrc, h->bnseg, h->val_csc, h->bval, h->stream);
     if (h->opts.center) launch_colmean(h->cp32, h->val_csc, h->n, h->m, h->mu, h->stream);
     check_launch();
   });

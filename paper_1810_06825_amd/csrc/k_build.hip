@@ -287,18 +287,17 @@ __global__ __launch_bounds__(256) void bcsc_tail_runs_kernel(const int32_t* cp, 
 }
 
 // A wave per segment copies its run of the mirror (rows, values, row-major positions).
+// a wave per run; brow is null when only the values move
 __global__ __launch_bounds__(256) void bcsc_copy_kernel(const int32_t* bptr, const int32_t* src, int64_t nseg,
                                                         const int32_t* row_csc, const float* val_csc,
-                                                        const int32_t* perm, int32_t* brow, float* bval,
-                                                        int32_t* bperm) {
+                                                        int32_t* brow, float* bval) {
   const int64_t seg = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (seg >= nseg) return;
   const int lane = threadIdx.x & 63;
   const int32_t d0 = bptr[seg], len = bptr[seg + 1] - d0, s0 = src[seg];
   for (int32_t i = lane; i < len; i += 64) {
-    brow[d0 + i] = row_csc[s0 + i];
+    if (brow) brow[d0 + i] = row_csc[s0 + i];
     bval[d0 + i] = val_csc[s0 + i];
-    bperm[d0 + i] = perm[s0 + i];
   }
 }
 
@@ -399,10 +398,15 @@ void launch_bcsc_runs(const int32_t* cp, const int32_t* row_csc, const int32_t* 
 }
 
 void launch_bcsc_copy(const int32_t* bptr, const int32_t* src, int64_t nseg, const int32_t* row_csc,
-                      const float* val_csc, const int32_t* perm, int32_t* brow, float* bval, int32_t* bperm,
-                      hipStream_t st) {
+                      const float* val_csc, int32_t* brow, float* bval, hipStream_t st) {
   if (nseg > 0)
-    bcsc_copy_kernel<<<grid_for(nseg, 4), 256, 0, st>>>(bptr, src, nseg, row_csc, val_csc, perm, brow, bval, bperm);
+    bcsc_copy_kernel<<<grid_for(nseg, 4), 256, 0, st>>>(bptr, src, nseg, row_csc, val_csc, brow, bval);
+}
+
+void launch_bcsc_values(const int32_t* bptr, const int32_t* src, int64_t nseg, const float* val_csc, float* bval,
+                        hipStream_t st) {
+  if (nseg > 0)
+    bcsc_copy_kernel<<<grid_for(nseg, 4), 256, 0, st>>>(bptr, src, nseg, nullptr, val_csc, nullptr, bval);
 }
 
 void launch_gather_values(const int32_t* perm, const float* val, int64_t nnz, float* out, hipStream_t st) {

@@ -44,13 +44,14 @@ void launch_gather_values(const int32_t* perm, const float* val, int64_t nnz, fl
 // Row-blocked order from the column-major mirror (cp, row_csc with rows ascending per column):
 // cnt/src[b * hh + h] = length and mirror start of hot column hotcol[h]'s run in row block b
 // (blocks of 2^shift rows), cnt/src[nblk * hh + t] = the whole tail column tailcol[t]. After
-// an exclusive scan of cnt into bptr, launch_bcsc_copy moves each run (rows, values, row-major
-// positions perm) to bptr[seg].
+// an exclusive scan of cnt into bptr, launch_bcsc_copy moves each run (rows and values) to
+// bptr[seg]; launch_bcsc_values moves the values alone (after new values reach the mirror).
 void launch_bcsc_runs(const int32_t* cp, const int32_t* row_csc, const int32_t* hotcol, const int32_t* tailcol,
                       int64_t hh, int64_t nblk, int64_t ntail, int shift, int32_t* cnt, int32_t* src, hipStream_t st);
 void launch_bcsc_copy(const int32_t* bptr, const int32_t* src, int64_t nseg, const int32_t* row_csc,
-                      const float* val_csc, const int32_t* perm, int32_t* brow, float* bval, int32_t* bperm,
-                      hipStream_t st);
+                      const float* val_csc, int32_t* brow, float* bval, hipStream_t st);
+void launch_bcsc_values(const int32_t* bptr, const int32_t* src, int64_t nseg, const float* val_csc, float* bval,
+                        hipStream_t st);
 
 // ---------------------------------------------------------------- blocked column order
 // (hot columns split by blocks of 2^kBcscRowShift rows; see k_bcsc.hip)
